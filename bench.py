@@ -1,0 +1,151 @@
+"""Throughput of the Green's-function Poisson solve on one MI355X.
+
+One step = one whole solve (all five passes) of the fully free 256^3 problem
+(FFT grid 512^3) on a seeded 32-Gaussian density already resident in HBM.
+Prints one JSON line with solves/s, the HBM roofline of the dominant pass and
+of the whole solve, the accuracy against the FP64 oracle, and the FP64 CPU
+oracle timed on this host's cores.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload free256]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "solves/s + % HBM roofline, 256^3 free BC; batched/split-prec vs plain FP32"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD spec
+PASS_NAMES = ["p1_r2c", "p2_fwd", "p3_conv", "p4_inv", "p5_c2r"]
+H = 0.3
+
+
+def pass_bytes(n, info):
+    """Algorithmic HBM bytes of each pass (each array read and written once)."""
+    S = info["S"]
+    p, q, r = info["axis_order"]
+    Hc = S[p] // 2 + 1
+    grid = n[0] * n[1] * n[2]
+    a1 = 8 * Hc * n[q] * n[r]
+    a2 = 8 * Hc * S[q] * n[r]
+    kf = 4 * Hc * (S[q] // 2 + 1) * (S[r] // 2 + 1)
+    return [4 * grid + a1, a1 + a2, 2 * a2 + kf, a2 + a1, a1 + 4 * grid]
+
+
+def cpu_baseline(rho32, n, bc, reps=3):
+    """The FP64 oracle on this host, K^F prebuilt (as the GPU's is)."""
+    import oracle
+    rho64 = rho32.astype(np.float64)
+    kf = oracle.kernel_fourier(n, bc, H)
+    workers = os.cpu_count() or 1
+    oracle.solve(rho64, bc, H, kf=kf, workers=workers)  # warm-up
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        V = oracle.solve(rho64, bc, H, kf=kf, workers=workers)
+        t.append(time.perf_counter() - t0)
+    med = float(np.median(t))
+    return V, {"value": 1.0 / med, "unit": "solves/s", "cores": workers, "kind": "oracle",
+               "sample": f"{reps} whole FP64 solves of the same workload after 1 warm-up "
+                         f"(scipy.fft, workers={workers}, K^F prebuilt); median {med:.3f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="free256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1211_5244_amd as P
+    from densities import WORKLOADS, workload_density
+
+    dev = torch.device("cuda:0")
+    P.load_library()
+    n, bc, rho = workload_density(args.workload, H)
+    rho32 = rho.astype(np.float32)
+    info = P.poisson_plan_describe(*n, bc)
+    plan = P.Plan(n, bc, H)
+    r = torch.from_numpy(rho32).to(dev)
+    V = torch.empty_like(r)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        plan.solve(r, V, stream)
+    torch.cuda.synchronize()
+
+    # timed region 1: back-to-back solves
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        P.poisson_solve(plan.handle, r, V, stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+
+    # timed region 2: the same solves with HIP events between the passes
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        for p in range(5):
+            P.poisson_solve_passes(plan.handle, r, V, p, p, stream)
+            ev[k][p + 1].record(stream)
+    torch.cuda.synchronize()
+    per_pass = [float(np.mean([ev[k][p].elapsed_time(ev[k][p + 1]) for k in range(args.steps)]))
+                for p in range(5)]
+
+    V_gpu = V.cpu().numpy()
+    pb = pass_bytes(n, info)
+    dom = int(np.argmax(per_pass))
+    achieved = pb[dom] / (per_pass[dom] * 1e-3) / 1e9
+    solve_gbs = info["alg_bytes"] / (ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": list(n), "bc_mask": bc, "S": list(info["S"]),
+                   "axis_order": list(info["axis_order"]), "h": H,
+                   "gaussians": WORKLOADS[args.workload]["gaussians"], "precision": "fp32"},
+        "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": pb[dom],
+                     "launch_ms": per_pass[dom]},
+        "solve_roofline": {"alg_bytes": info["alg_bytes"], "achieved": solve_gbs,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": solve_gbs / HBM_PEAK_GBS},
+        "passes_ms": dict(zip(PASS_NAMES, per_pass)),
+        "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
+    }
+    if not args.no_cpu_baseline:
+        V_ref, cb = cpu_baseline(rho32, n, bc)
+        out["cpu_baseline"] = cb
+        diff = V_gpu.astype(np.float64) - V_ref
+        out["rel_l2_vs_oracle"] = float(np.linalg.norm(diff) / np.linalg.norm(V_ref))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * poisson.h - C ABI of libpoisson, an MI355X (gfx950) Poisson solver for
+ * free, wire, surface and periodic boundary conditions.
+ *
+ * Operation (Dugan, Genovese, Goedecker, "A Customized 3D GPU Poisson Solver
+ * for Free Boundary Conditions"): the potential V of lap V = rho (Eq. 1) is
+ * the discrete convolution of rho with a Green's function K (Section 2,
+ * Eq. 2), evaluated in Fourier space as V^F = K^F rho^F (Eq. 3).  Axes with
+ * free boundary conditions are zero padded to twice their length (Section 2),
+ * so the FFT lengths are S_j = N_j B_j with B_j = 1 (periodic) or 2 (free)
+ * (Section 3).  The forward transform skips the all-zero half of every padded
+ * axis and the inverse transform crops each free axis back to N_j
+ * (Section 3, the customized 3D FFT); the first forward axis is real-to-complex
+ * and keeps S_p/2+1 coefficients (Section 3, last paragraphs).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays of grid values are contiguous float32 with x fastest:
+ *    element (i1, i2, i3) is at index i1 + n1*(i2 + n2*i3).  In PyTorch this
+ *    is a contiguous tensor of shape (n3, n2, n1).
+ *  - bc_mask bit j (POISSON_FREE_X/Y/Z) set = free along axis j, clear =
+ *    periodic along axis j.
+ *  - K^F convention: K^F = DFT_S(K_pad) (unnormalized forward DFT of the real,
+ *    even, padded kernel) and V = crop(IDFT_S(K^F * DFT_S(pad(rho)))) with
+ *    the inverse DFT carrying 1/(S1 S2 S3).  K^F is real and even in every
+ *    axis, so only the octant 0 <= k_j <= S_j/2 is passed, as float64 with k1
+ *    fastest: (S1/2+1)*(S2/2+1)*(S3/2+1) values.
+ *  - Device pointers are HIP device pointers of the device that was current
+ *    when the plan was created.  Streams are hipStream_t passed as void*;
+ *    NULL means the legacy default stream.
+ *  - Every call returns POISSON_OK (0) or a negative status and has no side
+ *    effects when it fails; poisson_last_error() gives a message for the
+ *    calling thread's last failure.  C++ exceptions never cross this ABI.
+ *  - Solves are asynchronous on the given stream; a device fault surfaces as
+ *    POISSON_E_HIP at a later call.
+ *  - A plan (or batch) may be used from one stream at a time: two solves of
+ *    one plan in flight on different streams share its workspace and race.
+ */
+#ifndef POISSON_H
+#define POISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct poisson_plan_s *poisson_plan_t;
+typedef struct poisson_batch_s *poisson_batch_t;
+
+enum {
+  POISSON_OK = 0,
+  POISSON_E_ARG = -1,         /* invalid argument (size, mask, spacing, pointer) */
+  POISSON_E_UNSUPPORTED = -2, /* an FFT length S_j outside the compiled set */
+  POISSON_E_NO_KERNEL = -3,   /* solve before poisson_kernel_set/_build */
+  POISSON_E_NOMEM = -4,       /* device allocation failed */
+  POISSON_E_HIP = -5,         /* a HIP runtime call failed */
+  POISSON_E_STATE = -6        /* call not valid in the object's current state */
+};
+
+enum { POISSON_FREE_X = 1, POISSON_FREE_Y = 2, POISSON_FREE_Z = 4 };
+
+enum {
+  POISSON_FP32 = 0,       /* float32 data, float32 arithmetic */
+  POISSON_SPLIT_FP16 = 1, /* reserved: radix stages on MFMA with fp16 hi+lo */
+  POISSON_SPLIT_BF16 = 2  /* reserved: radix stages on MFMA with bf16 splits */
+};
+
+/* Create a plan for an n1 x n2 x n3 grid with spacing h (> 0, finite).
+ * Each S_j = n_j * (1 + bit j of bc_mask) must be of the form 2^a 3^b with
+ * 4 <= S_j <= 1024 (n_j >= 2); otherwise POISSON_E_UNSUPPORTED.  Chooses
+ * the axis order (periodic axes first, free axes last in the forward
+ * transform: Section 3), builds the twiddle tables and allocates the device
+ * buffers of the plan (not the workspace; see poisson_set_workspace).  The
+ * plan is owned by the caller and released with poisson_plan_destroy. */
+int poisson_plan(poisson_plan_t *out, int n1, int n2, int n3, unsigned bc_mask, double h,
+                 int precision);
+
+/* Host-only description of the plan the same arguments would create; touches
+ * no device.  Any output pointer may be NULL.
+ *  axis_order: the forward axis order (p, q, r), 0 = x; p is the
+ *              real-to-complex axis.
+ *  S:          FFT lengths per physical axis (x, y, z).
+ *  workspace_bytes: device workspace a solve needs.
+ *  alg_bytes:  minimum HBM bytes one solve moves with five passes that each
+ *              read and write their data once (density, two intermediates,
+ *              potential, the K^F octant in float32). */
+int poisson_plan_describe(int n1, int n2, int n3, unsigned bc_mask, int precision,
+                          int axis_order[3], int S[3], size_t *workspace_bytes,
+                          double *alg_bytes);
+
+/* Host-only: per forward step s = 0, 1, 2 of the customized 3D FFT in the
+ * chosen order, the number of 1D transforms (rows) and their length, counted
+ * as in Section 3 (complex rows: the second step has S_p * N_r rows).  The
+ * inverse transform has the same counts in reverse order. */
+int poisson_plan_rows(int n1, int n2, int n3, unsigned bc_mask, long long rows[3],
+                      int lengths[3]);
+
+/* Hand the plan a caller-owned device workspace of at least the described
+ * size (256-byte aligned).  The plan stops using (and frees) any workspace it
+ * allocated itself.  Passing NULL returns the plan to self-allocation. */
+int poisson_set_workspace(poisson_plan_t plan, void *dev_ptr, size_t bytes);
+
+/* Set K^F from its float64 octant (layout above), on the host
+ * (is_device_ptr = 0) or the device (1).  The plan keeps the float64 octant
+ * and a float32 copy permuted to its pass order with 1/(S1 S2 S3) folded in
+ * (Section 3: the kernel is transposed once so the last forward transform
+ * needs no transpose).  Synchronous. */
+int poisson_kernel_set(poisson_plan_t plan, const double *kf_octant, int is_device_ptr);
+
+/* Build the default Green's function of the plan's boundary conditions on
+ * the device in float64 and set it as with poisson_kernel_set.  Asynchronous
+ * on `stream`.  Kernel family (the paper cites but does not define it): on
+ * periodic axes the spectral wave numbers k_j = 2 pi f_j / (S_j h), on the
+ * d free axes the sampled Green's function of (lap_d - kappa^2), kappa^2 =
+ * sum of periodic k_j^2, times h^d:
+ *   d=0: -1/kappa^2 (0 at k=0);  d=1: -exp(-kappa r)/(2 kappa), r/2 at kappa=0;
+ *   d=2: -K0(kappa r)/(2 pi), ln(r)/(2 pi) at kappa=0;  d=3: -1/(4 pi r),
+ * with O(h^4) origin weights, then the DFT along the free axes. */
+int poisson_kernel_build(poisson_plan_t plan, void *stream);
+
+/* Copy the plan's float64 K^F octant to host memory (same layout as
+ * poisson_kernel_set).  Synchronous. */
+int poisson_kernel_get(poisson_plan_t plan, double *kf_octant_host);
+
+/* V = K * rho for one density (device pointers, float32, layout above).
+ * rho == V (in place) is allowed.  Enqueues five passes on `stream` and
+ * returns without waiting; performs no allocation and no host sync, so it
+ * can be captured into a HIP graph once the workspace exists (the plan
+ * allocates its own workspace in poisson_kernel_set/_build). */
+int poisson_solve(poisson_plan_t plan, const float *rho_dev, float *V_dev, void *stream);
+
+/* Run only passes first..last (0..4) of poisson_solve, in order, on
+ * `stream`: 0 real-to-complex along p, 1 forward along q, 2 forward along r
+ * times K^F and inverse along r, 3 inverse along q, 4 complex-to-real along p
+ * (the step list of Section 3 with the transposes folded into the passes).
+ * Passes exchange data through the plan's workspace, so a later range sees
+ * the intermediates an earlier one left; running 0..4 equals poisson_solve.
+ * For per-pass timing and inspection. */
+int poisson_solve_passes(poisson_plan_t plan, const float *rho_dev, float *V_dev, int first,
+                         int last, void *stream);
+
+/* Release the plan and every device buffer it owns (not a caller workspace).
+ * Waits for the device to finish work that may use them. */
+int poisson_plan_destroy(poisson_plan_t plan);
+
+/* Batches of independent solves of different sizes and boundary conditions
+ * (Section 5 motivates many densities per run).  n holds 3*count sizes,
+ * bc_mask and h one entry per solve.  Solves with equal (n, bc_mask, h)
+ * share one plan and one K^F. */
+int poisson_batch_create(poisson_batch_t *out, int count, const int *n,
+                         const unsigned *bc_mask, const double *h, int precision);
+int poisson_batch_kernel_build(poisson_batch_t batch, void *stream);
+/* rho_ptrs_dev / V_ptrs_dev: host arrays of `count` device pointers. */
+int poisson_batch_solve(poisson_batch_t batch, const float *const *rho_ptrs,
+                        float *const *V_ptrs, void *stream);
+int poisson_batch_destroy(poisson_batch_t batch);
+
+/* Residual check in float64 on the device: *out = ||v - ref||_2 / ||ref||_2
+ * over `count` values, v float32 and ref float64, both device pointers.
+ * Synchronous (waits on `stream`). */
+int poisson_rel_l2(const float *v_dev, const double *ref_dev, size_t count, double *out,
+                   void *stream);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *poisson_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POISSON_H */

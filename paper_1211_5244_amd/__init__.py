@@ -1,0 +1,126 @@
+"""MI355X (gfx950) Poisson solver for free, wire, surface and periodic BCs.
+
+The solver computes V = crop(IDFT(K^F * DFT(pad(rho)))) with customized
+zero-skipping 3D FFTs (Dugan, Genovese, Goedecker, Sections 2-3) in the
+hand-written HIP kernels of libpoisson.so.  This package is its thin Python
+binding: the C entry points under their own names (`_lib`), plus `Plan` and
+`Batch`, which take PyTorch device tensors and pass their addresses.
+PyTorch is only used for device memory and streams.
+"""
+
+from __future__ import annotations
+
+from ._lib import (  # noqa: F401
+    EXPORTED,
+    LIB_PATH,
+    POISSON_FP32,
+    POISSON_FREE_X,
+    POISSON_FREE_Y,
+    POISSON_FREE_Z,
+    POISSON_SPLIT_BF16,
+    POISSON_SPLIT_FP16,
+    PoissonError,
+    load_library,
+    poisson_batch_create,
+    poisson_batch_destroy,
+    poisson_batch_kernel_build,
+    poisson_batch_solve,
+    poisson_kernel_build,
+    poisson_kernel_get,
+    poisson_kernel_set,
+    poisson_last_error,
+    poisson_plan,
+    poisson_plan_describe,
+    poisson_plan_destroy,
+    poisson_plan_rows,
+    poisson_rel_l2,
+    poisson_set_workspace,
+    poisson_solve,
+    poisson_solve_passes,
+)
+
+
+def _check_grid(t, n, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a device tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous float32 tensor")
+    if tuple(t.shape) != (n[2], n[1], n[0]):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {(n[2], n[1], n[0])}")
+
+
+class Plan:
+    """One grid size, boundary-condition mask and spacing.
+
+    rho and V are float32 device tensors of shape (n3, n2, n1) (x fastest)."""
+
+    def __init__(self, n, bc_mask, h, precision=POISSON_FP32, build_kernel=True, stream=None):
+        self.n = tuple(int(v) for v in n)
+        self.bc_mask = int(bc_mask)
+        self.h = float(h)
+        self.info = poisson_plan_describe(*self.n, self.bc_mask, precision)
+        self.handle = poisson_plan(*self.n, self.bc_mask, self.h, precision)
+        if build_kernel:
+            poisson_kernel_build(self.handle, stream)
+
+    @property
+    def S(self):
+        return self.info["S"]
+
+    def set_kernel(self, kf_octant):
+        poisson_kernel_set(self.handle, kf_octant)
+
+    def kernel(self):
+        return poisson_kernel_get(self.handle, self.S)
+
+    def solve(self, rho, V=None, stream=None):
+        import torch
+        _check_grid(rho, self.n, "rho")
+        if V is None:
+            V = torch.empty_like(rho)
+        _check_grid(V, self.n, "V")
+        if stream is None:
+            stream = torch.cuda.current_stream(rho.device)
+        poisson_solve(self.handle, rho, V, stream)
+        return V
+
+    def close(self):
+        if getattr(self, "handle", None):
+            poisson_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent solves (sizes and BC masks may differ)."""
+
+    def __init__(self, n_list, bc_list, h_list, precision=POISSON_FP32, stream=None):
+        self.n_list = [tuple(int(v) for v in n) for n in n_list]
+        self.handle = poisson_batch_create(self.n_list, list(bc_list), list(h_list), precision)
+        poisson_batch_kernel_build(self.handle, stream)
+
+    def solve(self, rho_list, V_list, stream=None):
+        import torch
+        for i, (r, v) in enumerate(zip(rho_list, V_list)):
+            _check_grid(r, self.n_list[i], f"rho[{i}]")
+            _check_grid(v, self.n_list[i], f"V[{i}]")
+        if stream is None:
+            stream = torch.cuda.current_stream(rho_list[0].device)
+        poisson_batch_solve(self.handle, rho_list, V_list, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            poisson_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

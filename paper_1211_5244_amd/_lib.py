@@ -1,0 +1,207 @@
+"""ctypes binding of libpoisson's C ABI (include/poisson.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  There is no fallback; if the library is missing, loading it raises.
+Function names and arguments mirror the C entry points.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpoisson.so")
+
+POISSON_OK = 0
+POISSON_E_ARG = -1
+POISSON_E_UNSUPPORTED = -2
+POISSON_E_NO_KERNEL = -3
+POISSON_E_NOMEM = -4
+POISSON_E_HIP = -5
+POISSON_E_STATE = -6
+
+POISSON_FREE_X, POISSON_FREE_Y, POISSON_FREE_Z = 1, 2, 4
+POISSON_FP32, POISSON_SPLIT_FP16, POISSON_SPLIT_BF16 = 0, 1, 2
+
+# every symbol include/poisson.h declares
+EXPORTED = (
+    "poisson_plan", "poisson_plan_describe", "poisson_plan_rows", "poisson_set_workspace",
+    "poisson_kernel_set", "poisson_kernel_build", "poisson_kernel_get", "poisson_solve",
+    "poisson_solve_passes",
+    "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
+    "poisson_batch_solve", "poisson_batch_destroy", "poisson_rel_l2", "poisson_last_error",
+)
+
+
+class PoissonError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_u = ctypes.c_uint
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+
+
+def load_library(path=None):
+    """Load libpoisson.so (built in-tree by paper_1211_5244_amd.build)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -m paper_1211_5244_amd.build`")
+    lib = ctypes.CDLL(p)
+    sig = {
+        "poisson_plan": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _u, _d, _i]),
+        "poisson_plan_describe": (_i, [_i, _i, _i, _u, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
+                                       ctypes.POINTER(_sz), ctypes.POINTER(_d)]),
+        "poisson_plan_rows": (_i, [_i, _i, _i, _u, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_i)]),
+        "poisson_set_workspace": (_i, [_vp, _vp, _sz]),
+        "poisson_kernel_set": (_i, [_vp, _vp, _i]),
+        "poisson_kernel_build": (_i, [_vp, _vp]),
+        "poisson_kernel_get": (_i, [_vp, _vp]),
+        "poisson_solve": (_i, [_vp, _vp, _vp, _vp]),
+        "poisson_solve_passes": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
+        "poisson_plan_destroy": (_i, [_vp]),
+        "poisson_batch_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), ctypes.POINTER(_u),
+                                      ctypes.POINTER(_d), _i]),
+        "poisson_batch_kernel_build": (_i, [_vp, _vp]),
+        "poisson_batch_solve": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+        "poisson_batch_destroy": (_i, [_vp]),
+        "poisson_rel_l2": (_i, [_vp, _vp, _sz, ctypes.POINTER(_d), _vp]),
+        "poisson_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def poisson_last_error():
+    return load_library().poisson_last_error().decode()
+
+
+def _check(rc):
+    if rc != POISSON_OK:
+        raise PoissonError(rc, poisson_last_error())
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(f"cannot take the address of {type(x).__name__}")
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream on ROCm wraps a hipStream_t
+
+
+def poisson_plan(n1, n2, n3, bc_mask, h, precision=POISSON_FP32):
+    out = _vp()
+    _check(load_library().poisson_plan(ctypes.byref(out), n1, n2, n3, bc_mask, h, precision))
+    return out.value
+
+
+def poisson_plan_describe(n1, n2, n3, bc_mask, precision=POISSON_FP32):
+    order = (_i * 3)()
+    S = (_i * 3)()
+    ws = _sz()
+    alg = _d()
+    _check(load_library().poisson_plan_describe(n1, n2, n3, bc_mask, precision, order, S,
+                                                ctypes.byref(ws), ctypes.byref(alg)))
+    return dict(axis_order=tuple(order), S=tuple(S), workspace_bytes=ws.value, alg_bytes=alg.value)
+
+
+def poisson_plan_rows(n1, n2, n3, bc_mask):
+    rows = (ctypes.c_longlong * 3)()
+    lens = (_i * 3)()
+    _check(load_library().poisson_plan_rows(n1, n2, n3, bc_mask, rows, lens))
+    return tuple(rows), tuple(lens)
+
+
+def poisson_set_workspace(plan, dev_ptr, nbytes):
+    _check(load_library().poisson_set_workspace(plan, _ptr(dev_ptr), nbytes))
+
+
+def poisson_kernel_set(plan, kf_octant, is_device_ptr=None):
+    """kf_octant: float64 octant as a numpy array (host) or a device tensor."""
+    if isinstance(kf_octant, np.ndarray):
+        arr = np.ascontiguousarray(kf_octant, dtype=np.float64)
+        _check(load_library().poisson_kernel_set(plan, arr.ctypes.data, 0))
+        return
+    dev = 1 if is_device_ptr is None else int(is_device_ptr)
+    _check(load_library().poisson_kernel_set(plan, _ptr(kf_octant), dev))
+
+
+def poisson_kernel_build(plan, stream=None):
+    _check(load_library().poisson_kernel_build(plan, _stream(stream)))
+
+
+def poisson_kernel_get(plan, S):
+    out = np.empty((S[2] // 2 + 1, S[1] // 2 + 1, S[0] // 2 + 1), dtype=np.float64)
+    _check(load_library().poisson_kernel_get(plan, out.ctypes.data))
+    return out
+
+
+def poisson_solve(plan, rho, V, stream=None):
+    _check(load_library().poisson_solve(plan, _ptr(rho), _ptr(V), _stream(stream)))
+
+
+def poisson_solve_passes(plan, rho, V, first, last, stream=None):
+    _check(load_library().poisson_solve_passes(plan, _ptr(rho), _ptr(V), first, last, _stream(stream)))
+
+
+def poisson_plan_destroy(plan):
+    _check(load_library().poisson_plan_destroy(plan))
+
+
+def poisson_batch_create(n_list, bc_list, h_list, precision=POISSON_FP32):
+    count = len(n_list)
+    n = (_i * (3 * count))(*[int(v) for nn in n_list for v in nn])
+    bc = (_u * count)(*[int(b) for b in bc_list])
+    h = (_d * count)(*[float(x) for x in h_list])
+    out = _vp()
+    _check(load_library().poisson_batch_create(ctypes.byref(out), count, n, bc, h, precision))
+    return out.value
+
+
+def poisson_batch_kernel_build(batch, stream=None):
+    _check(load_library().poisson_batch_kernel_build(batch, _stream(stream)))
+
+
+def poisson_batch_solve(batch, rho_list, V_list, stream=None):
+    count = len(rho_list)
+    r = (_vp * count)(*[_ptr(x) for x in rho_list])
+    v = (_vp * count)(*[_ptr(x) for x in V_list])
+    _check(load_library().poisson_batch_solve(batch, r, v, _stream(stream)))
+
+
+def poisson_batch_destroy(batch):
+    _check(load_library().poisson_batch_destroy(batch))
+
+
+def poisson_rel_l2(v, ref, count, stream=None):
+    out = _d()
+    _check(load_library().poisson_rel_l2(_ptr(v), _ptr(ref), count, ctypes.byref(out), _stream(stream)))
+    return out.value

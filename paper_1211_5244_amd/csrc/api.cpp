@@ -1,0 +1,460 @@
+// api.cpp - the C ABI of libpoisson (declared in include/poisson.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/poisson.h"
+#include "kernels.h"
+#include "plan.h"
+
+using psn::Geometry;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(e == hipErrorOutOfMemory ? POISSON_E_NOMEM : POISSON_E_HIP, m);
+}
+
+// Runs a call with the plan's device current and restores the caller's.
+struct DeviceScope {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+#define PSN_TRY_HIP(call, what)                 \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+}  // namespace
+
+struct poisson_plan_s {
+  Geometry g;
+  double h = 0;
+  int precision = POISSON_FP32;
+  int device = 0;
+  float2 *tw[3] = {nullptr, nullptr, nullptr};     // per physical axis (shared by equal lengths)
+  double *cos_tab[3] = {nullptr, nullptr, nullptr};
+  std::vector<void *> owned;                        // every device buffer the plan allocated
+  double *kf64 = nullptr;
+  float *kf32 = nullptr;
+  void *ws = nullptr;
+  bool own_ws = false;
+  bool kernel_ready = false;
+};
+
+struct poisson_batch_s {
+  std::vector<poisson_plan_t> plans;  // unique problems
+  std::vector<int> which;             // solve i uses plans[which[i]]
+  int device = 0;
+};
+
+namespace {
+
+int check_precision(int precision) {
+  if (precision == POISSON_FP32) return POISSON_OK;
+  if (precision == POISSON_SPLIT_FP16 || precision == POISSON_SPLIT_BF16)
+    return fail(POISSON_E_UNSUPPORTED, "split-precision modes are not available in this build");
+  return fail(POISSON_E_ARG, "precision must be POISSON_FP32, POISSON_SPLIT_FP16 or POISSON_SPLIT_BF16");
+}
+
+int plan_alloc(poisson_plan_t P, void **ptr, size_t bytes, const char *what) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hip_fail(e, what);
+  }
+  P->owned.push_back(p);
+  *ptr = p;
+  return POISSON_OK;
+}
+
+void plan_free_all(poisson_plan_t P) {
+  for (void *p : P->owned) (void)hipFree(p);
+  P->owned.clear();
+}
+
+int ensure_workspace(poisson_plan_t P) {
+  if (P->ws) return POISSON_OK;
+  void *p = nullptr;
+  int rc = plan_alloc(P, &p, P->g.ws_bytes, "hipMalloc(workspace)");
+  if (rc) return rc;
+  P->ws = p;
+  P->own_ws = true;
+  return POISSON_OK;
+}
+
+// exp(-2 pi i n / L), n = 0..L-1, evaluated in long double, rounded once
+std::vector<float2> twiddle_table(int L) {
+  std::vector<float2> t(L);
+  const long double two_pi = 6.283185307179586476925286766559L;
+  for (int n = 0; n < L; ++n) {
+    const long double a = two_pi * n / L;
+    t[n] = make_float2(float(std::cos(a)), float(-std::sin(a)));
+  }
+  return t;
+}
+
+std::vector<double> cosine_table(int S) {
+  std::vector<double> t(S);
+  const long double two_pi = 6.283185307179586476925286766559L;
+  for (int n = 0; n < S; ++n) t[n] = double(std::cos(two_pi * n / S));
+  return t;
+}
+
+int finish_kernel(poisson_plan_t P, hipStream_t s) {
+  hipError_t e = psn::launch_kernel_permute(P->g, P->kf64, P->kf32, s);
+  if (e != hipSuccess) return hip_fail(e, "K^F permute launch");
+  P->kernel_ready = true;
+  return POISSON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *poisson_last_error(void) { return g_last_error.c_str(); }
+
+int poisson_plan_describe(int n1, int n2, int n3, unsigned bc_mask, int precision,
+                          int axis_order[3], int S[3], size_t *workspace_bytes,
+                          double *alg_bytes) {
+  try {
+    Geometry g;
+    std::string err;
+    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err);
+    if (rc) return fail(rc, err);
+    rc = check_precision(precision);
+    if (rc) return rc;
+    for (int j = 0; j < 3; ++j) {
+      if (axis_order) axis_order[j] = g.order[j];
+      if (S) S[j] = g.S[j];
+    }
+    if (workspace_bytes) *workspace_bytes = g.ws_bytes;
+    if (alg_bytes) *alg_bytes = g.alg_bytes;
+    return POISSON_OK;
+  } catch (...) {
+    return fail(POISSON_E_STATE, "unexpected exception");
+  }
+}
+
+int poisson_plan_rows(int n1, int n2, int n3, unsigned bc_mask, long long rows[3],
+                      int lengths[3]) {
+  try {
+    Geometry g;
+    std::string err;
+    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err);
+    if (rc) return fail(rc, err);
+    const int p = g.order[0], q = g.order[1], r = g.order[2];
+    const long long R[3] = {(long long)g.n[q] * g.n[r], (long long)g.S[p] * g.n[r],
+                            (long long)g.S[p] * g.S[q]};
+    const int Ls[3] = {g.S[p], g.S[q], g.S[r]};
+    for (int k = 0; k < 3; ++k) {
+      if (rows) rows[k] = R[k];
+      if (lengths) lengths[k] = Ls[k];
+    }
+    return POISSON_OK;
+  } catch (...) {
+    return fail(POISSON_E_STATE, "unexpected exception");
+  }
+}
+
+int poisson_plan(poisson_plan_t *out, int n1, int n2, int n3, unsigned bc_mask, double h,
+                 int precision) {
+  try {
+    if (!out) return fail(POISSON_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(POISSON_E_ARG, "spacing h must be positive and finite");
+    Geometry g;
+    std::string err;
+    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err);
+    if (rc) return fail(rc, err);
+    rc = check_precision(precision);
+    if (rc) return rc;
+
+    poisson_plan_t P = new (std::nothrow) poisson_plan_s();
+    if (!P) return fail(POISSON_E_NOMEM, "host allocation failed");
+    P->g = g;
+    P->h = h;
+    P->precision = precision;
+    hipError_t e = hipGetDevice(&P->device);
+    if (e != hipSuccess) {
+      delete P;
+      return hip_fail(e, "hipGetDevice");
+    }
+    auto cleanup = [&](int code) {
+      plan_free_all(P);
+      delete P;
+      return code;
+    };
+    // twiddle and cosine tables, one per distinct length
+    for (int j = 0; j < 3; ++j) {
+      int same = -1;
+      for (int k = 0; k < j; ++k)
+        if (g.S[k] == g.S[j]) same = k;
+      if (same >= 0) {
+        P->tw[j] = P->tw[same];
+        P->cos_tab[j] = P->cos_tab[same];
+        continue;
+      }
+      void *p = nullptr;
+      if ((rc = plan_alloc(P, &p, sizeof(float2) * g.S[j], "hipMalloc(twiddles)"))) return cleanup(rc);
+      P->tw[j] = static_cast<float2 *>(p);
+      std::vector<float2> t = twiddle_table(g.S[j]);
+      e = hipMemcpy(p, t.data(), sizeof(float2) * t.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy(twiddles)"));
+      if ((rc = plan_alloc(P, &p, sizeof(double) * g.S[j], "hipMalloc(cosines)"))) return cleanup(rc);
+      P->cos_tab[j] = static_cast<double *>(p);
+      std::vector<double> c = cosine_table(g.S[j]);
+      e = hipMemcpy(p, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy(cosines)"));
+    }
+    void *p = nullptr;
+    if ((rc = plan_alloc(P, &p, sizeof(double) * g.kf_octant, "hipMalloc(K^F float64)"))) return cleanup(rc);
+    P->kf64 = static_cast<double *>(p);
+    if ((rc = plan_alloc(P, &p, sizeof(float) * g.kf_internal, "hipMalloc(K^F float32)"))) return cleanup(rc);
+    P->kf32 = static_cast<float *>(p);
+    *out = P;
+    return POISSON_OK;
+  } catch (...) {
+    return fail(POISSON_E_STATE, "unexpected exception");
+  }
+}
+
+int poisson_set_workspace(poisson_plan_t P, void *dev_ptr, size_t bytes) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  if (dev_ptr && bytes < P->g.ws_bytes)
+    return fail(POISSON_E_ARG, "workspace smaller than poisson_plan_describe's workspace_bytes");
+  if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) % 256) != 0)
+    return fail(POISSON_E_ARG, "workspace must be 256-byte aligned");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  if (P->own_ws && P->ws) {
+    PSN_TRY_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    for (size_t i = 0; i < P->owned.size(); ++i) {
+      if (P->owned[i] == P->ws) {
+        (void)hipFree(P->ws);
+        P->owned.erase(P->owned.begin() + i);
+        break;
+      }
+    }
+  }
+  P->ws = dev_ptr;
+  P->own_ws = false;
+  return POISSON_OK;
+}
+
+int poisson_kernel_set(poisson_plan_t P, const double *kf, int is_device_ptr) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  if (!kf) return fail(POISSON_E_ARG, "K^F pointer is NULL");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  int rc = ensure_workspace(P);
+  if (rc) return rc;
+  PSN_TRY_HIP(hipMemcpy(P->kf64, kf, sizeof(double) * P->g.kf_octant,
+                        is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice),
+              "hipMemcpy(K^F)");
+  rc = finish_kernel(P, nullptr);
+  if (rc) return rc;
+  PSN_TRY_HIP(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+  return POISSON_OK;
+}
+
+int poisson_kernel_build(poisson_plan_t P, void *stream) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  int rc = ensure_workspace(P);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // float64 scratch for the DCT ping-pong
+  void *tmp = nullptr;
+  PSN_TRY_HIP(hipMalloc(&tmp, sizeof(double) * P->g.kf_octant), "hipMalloc(K^F scratch)");
+  const double *tabs[3] = {P->cos_tab[0], P->cos_tab[1], P->cos_tab[2]};
+  hipError_t e = psn::launch_kernel_build(P->g, P->h, P->kf64, static_cast<double *>(tmp), tabs, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "K^F build");
+  return finish_kernel(P, s);
+}
+
+int poisson_kernel_get(poisson_plan_t P, double *host) {
+  if (!P || !host) return fail(POISSON_E_ARG, "NULL argument");
+  if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "no K^F has been set or built");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  PSN_TRY_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  PSN_TRY_HIP(hipMemcpy(host, P->kf64, sizeof(double) * P->g.kf_octant, hipMemcpyDeviceToHost),
+              "hipMemcpy(K^F to host)");
+  return POISSON_OK;
+}
+
+int poisson_solve(poisson_plan_t P, const float *rho, float *V, void *stream) {
+  return poisson_solve_passes(P, rho, V, 0, 4, stream);
+}
+
+int poisson_solve_passes(poisson_plan_t P, const float *rho, float *V, int first, int last,
+                         void *stream) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  if (first < 0 || last > 4 || first > last) return fail(POISSON_E_ARG, "pass range must satisfy 0 <= first <= last <= 4");
+  if (!rho || !V) return fail(POISSON_E_ARG, "rho or V is NULL");
+  if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "no K^F has been set or built");
+  if (!P->ws) return fail(POISSON_E_STATE, "no workspace");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geometry &g = P->g;
+  char *ws = static_cast<char *>(P->ws);
+  float2 *A1 = reinterpret_cast<float2 *>(ws);
+  float2 *A2 = reinterpret_cast<float2 *>(ws + g.a1_bytes);
+  const int p = g.order[0], q = g.order[1], r = g.order[2];
+  const int Sq = g.S[q];
+  struct Step {
+    const void *in;
+    void *out;
+    const float2 *tw;
+  } steps[5] = {{rho, A1, P->tw[p]}, {A1, A2, P->tw[q]}, {A2, A2, P->tw[r]},
+                {A2, A1, P->tw[q]}, {A1, V, P->tw[p]}};
+  for (int k = first; k <= last; ++k) {
+    hipError_t e = psn::launch_pass(g.pass[k], steps[k].in, steps[k].out, steps[k].tw, P->kf32, Sq, s);
+    if (e != hipSuccess) return hip_fail(e, "pass launch");
+  }
+  return POISSON_OK;
+}
+
+int poisson_plan_destroy(poisson_plan_t P) {
+  if (!P) return POISSON_OK;
+  {
+    DeviceScope ds(P->device);
+    (void)hipDeviceSynchronize();
+    plan_free_all(P);
+  }
+  delete P;
+  return POISSON_OK;
+}
+
+int poisson_batch_create(poisson_batch_t *out, int count, const int *n, const unsigned *bc_mask,
+                         const double *h, int precision) {
+  try {
+    if (!out) return fail(POISSON_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (count <= 0 || !n || !bc_mask || !h) return fail(POISSON_E_ARG, "empty batch or NULL array");
+    int rc = check_precision(precision);
+    if (rc) return rc;
+    // validate every entry before allocating anything
+    for (int i = 0; i < count; ++i) {
+      Geometry g;
+      std::string err;
+      rc = psn::build_geometry(n[3 * i], n[3 * i + 1], n[3 * i + 2], bc_mask[i], g, err);
+      if (rc) return fail(rc, "batch entry " + std::to_string(i) + ": " + err);
+      if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+        return fail(POISSON_E_ARG, "batch entry " + std::to_string(i) + ": bad spacing");
+    }
+    poisson_batch_t B = new (std::nothrow) poisson_batch_s();
+    if (!B) return fail(POISSON_E_NOMEM, "host allocation failed");
+    (void)hipGetDevice(&B->device);
+    std::map<std::tuple<int, int, int, unsigned, double>, int> index;
+    for (int i = 0; i < count; ++i) {
+      auto key = std::make_tuple(n[3 * i], n[3 * i + 1], n[3 * i + 2], bc_mask[i], h[i]);
+      auto it = index.find(key);
+      if (it == index.end()) {
+        poisson_plan_t P = nullptr;
+        rc = poisson_plan(&P, n[3 * i], n[3 * i + 1], n[3 * i + 2], bc_mask[i], h[i], precision);
+        if (rc) {
+          std::string msg = g_last_error;
+          for (auto *pp : B->plans) poisson_plan_destroy(pp);
+          delete B;
+          return fail(rc, msg);
+        }
+        it = index.emplace(key, int(B->plans.size())).first;
+        B->plans.push_back(P);
+      }
+      B->which.push_back(it->second);
+    }
+    *out = B;
+    return POISSON_OK;
+  } catch (...) {
+    return fail(POISSON_E_STATE, "unexpected exception");
+  }
+}
+
+int poisson_batch_kernel_build(poisson_batch_t B, void *stream) {
+  if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  for (auto *P : B->plans) {
+    int rc = poisson_kernel_build(P, stream);
+    if (rc) return rc;
+  }
+  return POISSON_OK;
+}
+
+int poisson_batch_solve(poisson_batch_t B, const float *const *rho, float *const *V, void *stream) {
+  if (!B || !rho || !V) return fail(POISSON_E_ARG, "NULL argument");
+  for (size_t i = 0; i < B->which.size(); ++i)
+    if (!rho[i] || !V[i]) return fail(POISSON_E_ARG, "batch entry " + std::to_string(i) + ": NULL pointer");
+  for (auto *P : B->plans)
+    if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "batch kernels not built");
+  for (size_t i = 0; i < B->which.size(); ++i) {
+    int rc = poisson_solve(B->plans[B->which[i]], rho[i], V[i], stream);
+    if (rc) return rc;
+  }
+  return POISSON_OK;
+}
+
+int poisson_batch_destroy(poisson_batch_t B) {
+  if (!B) return POISSON_OK;
+  for (auto *P : B->plans) poisson_plan_destroy(P);
+  delete B;
+  return POISSON_OK;
+}
+
+int poisson_rel_l2(const float *v, const double *ref, size_t count, double *out, void *stream) {
+  if (!v || !ref || !out || count == 0) return fail(POISSON_E_ARG, "NULL argument or empty input");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int max_blocks = 1024;
+  double *partials = nullptr;
+  PSN_TRY_HIP(hipMalloc(&partials, sizeof(double) * 2 * max_blocks), "hipMalloc(partials)");
+  int blocks = 0;
+  hipError_t e = psn::launch_rel_l2_partials(v, ref, count, partials, max_blocks, &blocks, s);
+  std::vector<double> host(2 * max_blocks);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), partials, sizeof(double) * 2 * blocks,
+                                          hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(partials);
+  if (e != hipSuccess) return hip_fail(e, "relative L2 norm");
+  double num = 0, den = 0;
+  for (int b = 0; b < blocks; ++b) {
+    num += host[2 * b];
+    den += host[2 * b + 1];
+  }
+  *out = den > 0 ? std::sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+  return POISSON_OK;
+}
+
+}  // extern "C"

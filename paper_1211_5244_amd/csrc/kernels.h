@@ -1,0 +1,34 @@
+// kernels.h - host-callable launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace psn {
+
+// One pass of the solve on `stream`: reads `in`, writes `out` (complex
+// intermediates are float2, the density and potential float).  `tw` is the
+// table exp(-2 pi i n / L), n = 0..L-1, of the pass's length; `kf` is the
+// float32 K^F in pass order (conv pass only).  Returns a hipError_t.
+hipError_t launch_pass(const Pass &P, const void *in, void *out, const float2 *tw,
+                       const float *kf, int S_q, hipStream_t stream);
+
+// float64 K^F octant of the default Green's function (layout of the C ABI:
+// k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.
+// cos_tabs[j]: device table cos(2 pi n / S_j), n = 0..S_j-1, for each axis.
+hipError_t launch_kernel_build(const Geometry &g, double h, double *kf64, double *tmp,
+                               const double *const cos_tabs[3], hipStream_t stream);
+
+// float32 K^F in pass order [k_p][k_q'][k_r'] with 1/(S1 S2 S3) folded in,
+// from the float64 octant.
+hipError_t launch_kernel_permute(const Geometry &g, const double *kf64, float *kf32,
+                                 hipStream_t stream);
+
+// partial sums of (v - ref)^2 and ref^2 in float64: writes 2*blocks doubles
+// to `partials`; blocks is the returned count (<= max_blocks).
+hipError_t launch_rel_l2_partials(const float *v, const double *ref, size_t count,
+                                  double *partials, int max_blocks, int *blocks,
+                                  hipStream_t stream);
+
+}  // namespace psn

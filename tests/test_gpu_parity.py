@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path against the FP64 oracle.
+
+Every case feeds the same float32-rounded density to both sides (seeded
+Gaussian mixtures or seeded noise).  The bar is the relative L2 error of
+1e-6 (float32 solver against the float64 definition), plus an element-wise
+envelope; the float64 K^F built on the GPU must match the oracle's to 1e-12.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1211_5244_amd as P
+from densities import WORKLOADS, draw_gaussians, gaussian_mixture, workload_density
+
+pytestmark = pytest.mark.gpu
+
+H = 0.3
+REL_L2 = 1e-6        # float32 solver vs float64 definition
+ELEM = 4e-6          # |dV_i| <= ELEM * max|V_ref|
+KF_REL = 1e-12       # float64 kernel build vs float64 oracle kernel
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.load_library()  # raises if the HIP library is missing: no fallback
+    return torch
+
+
+def _density(n, bc, seed, count=6):
+    gs = draw_gaussians(n, H, count, (1.0, 3.0), seed)
+    rho = gaussian_mixture(n, bc, H, gs)
+    return rho.astype(np.float32)
+
+
+def _gpu_solve(torch, n, bc, rho32, plan=None):
+    plan = plan or P.Plan(n, bc, H)
+    r = torch.from_numpy(rho32).cuda()
+    V = plan.solve(r)
+    torch.cuda.synchronize()
+    return V.cpu().numpy(), plan
+
+
+def _check(V, ref, what):
+    err = oracle.rel_l2(V, ref)
+    emax = float(np.max(np.abs(V.astype(np.float64) - ref)) / np.max(np.abs(ref)))
+    print(f"{what}: relL2 {err:.3e} max elementwise {emax:.3e}", flush=True)
+    assert err <= REL_L2, (what, err)
+    assert emax <= ELEM, (what, emax)
+    return err
+
+
+SMALL_SHAPES = [(32, 24, 48), (12, 64, 16), (6, 8, 12)]
+
+
+@pytest.mark.parametrize("bc", range(8))
+@pytest.mark.parametrize("n", [(6, 8, 12), (16, 16, 16), (12, 48, 32)])
+def test_kernel_build_matches_oracle(torch_dev, n, bc):
+    plan = P.Plan(n, bc, H)
+    kf = plan.kernel()
+    ref = oracle.kernel_octant(n, bc, H)
+    d = float(np.max(np.abs(kf - ref)) / np.max(np.abs(ref)))
+    print(f"K^F {n} bc={bc}: {d:.2e}", flush=True)
+    assert d <= KF_REL
+
+
+@pytest.mark.parametrize("bc", range(8))
+@pytest.mark.parametrize("n", SMALL_SHAPES)
+def test_solve_parity_small(torch_dev, n, bc):
+    rho = _density(n, bc, seed=100 + bc)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"{n} bc={bc}")
+
+
+@pytest.mark.parametrize("bc", range(8))
+def test_solve_parity_noise(torch_dev, bc):
+    """Unstructured density: every Fourier mode carries weight."""
+    n = (24, 32, 16)
+    rng = np.random.default_rng(bc)
+    rho = rng.standard_normal((n[2], n[1], n[0]))
+    if bc == 0:
+        rho -= rho.mean()
+    rho = rho.astype(np.float32)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"noise {n} bc={bc}")
+
+
+@pytest.mark.parametrize("name", ["free128", "wire128", "surface128", "periodic128"])
+def test_solve_parity_128(torch_dev, name):
+    n, bc, rho = workload_density(name)
+    rho = rho.astype(np.float32)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), name)
+
+
+@pytest.mark.parametrize("n,bc", [((64, 96, 48), 7), ((64, 96, 48), 3), ((96, 64, 48), 2),
+                                  ((48, 64, 96), 0), ((96, 48, 64), 5), ((48, 96, 64), 6),
+                                  ((64, 48, 96), 1), ((96, 96, 48), 4)])
+def test_solve_parity_mixed_radix(torch_dev, n, bc):
+    rho = _density(n, bc, seed=7, count=8)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"{n} bc={bc}")
+
+
+def test_kernel_set_from_oracle_octant(torch_dev):
+    """poisson_kernel_set with the oracle's octant gives the same solve."""
+    n, bc = (32, 24, 48), 3
+    rho = _density(n, bc, seed=3)
+    V_build, _ = _gpu_solve(torch_dev, n, bc, rho)
+    plan = P.Plan(n, bc, H, build_kernel=False)
+    plan.set_kernel(oracle.kernel_octant(n, bc, H))
+    V_set, _ = _gpu_solve(torch_dev, n, bc, rho, plan)
+    assert oracle.rel_l2(V_set, V_build) < 1e-7
+    _check(V_set, oracle.solve(rho.astype(np.float64), bc, H), "kernel_set")
+
+
+def test_in_place_and_deterministic(torch_dev):
+    torch = torch_dev
+    n, bc = (48, 32, 64), 7
+    rho = _density(n, bc, seed=5)
+    plan = P.Plan(n, bc, H)
+    r = torch.from_numpy(rho).cuda()
+    V1 = plan.solve(r)
+    V2 = plan.solve(r)
+    x = r.clone()
+    plan.solve(x, x)
+    torch.cuda.synchronize()
+    assert torch.equal(V1, V2)
+    assert torch.equal(V1, x)
+
+
+def test_solve_before_kernel_is_an_error(torch_dev):
+    torch = torch_dev
+    plan = P.Plan((16, 16, 16), 7, H, build_kernel=False)
+    r = torch.zeros((16, 16, 16), device="cuda")
+    with pytest.raises(P.PoissonError) as e:
+        plan.solve(r)
+    assert e.value.code == P._lib.POISSON_E_NO_KERNEL
+
+
+def test_batch_equals_single_solves(torch_dev):
+    torch = torch_dev
+    cases = [((32, 32, 32), 7), ((48, 48, 48), 3), ((32, 32, 32), 7), ((64, 64, 64), 2),
+             ((16, 16, 16), 0), ((48, 48, 48), 3)]
+    rhos = [torch.from_numpy(_density(n, bc, seed=50 + i)).cuda() for i, (n, bc) in enumerate(cases)]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases))
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for i, (n, bc) in enumerate(cases):
+        single = P.Plan(n, bc, H).solve(rhos[i])
+        torch.cuda.synchronize()
+        assert torch.equal(single, Vs[i]), i
+
+
+def test_gpu_residual_norm_matches_host(torch_dev):
+    torch = torch_dev
+    n, bc = (32, 32, 32), 7
+    rho = _density(n, bc, seed=9)
+    V, _ = _gpu_solve(torch, n, bc, rho)
+    ref = oracle.solve(rho.astype(np.float64), bc, H)
+    dev = P.poisson_rel_l2(torch.from_numpy(V).cuda(), torch.from_numpy(ref).cuda(), V.size)
+    assert dev == pytest.approx(oracle.rel_l2(V, ref), rel=1e-9)
+
+
+# ------------------------------------------------------------- full sizes
+def _direct_free_samples(rho, h, points):
+    """V at a few points by the direct sum of Eq. 2 with the sampled Coulomb
+    kernel (free BCs), float64, no FFT."""
+    n3, n2, n1 = rho.shape
+    z = np.arange(n3)[:, None, None]
+    y = np.arange(n2)[None, :, None]
+    x = np.arange(n1)[None, None, :]
+    out = []
+    for (i1, i2, i3) in points:
+        m2 = (x - i1) ** 2 + (y - i2) ** 2 + (z - i3) ** 2
+        k = np.where(m2 > 0, -h * h / (4 * np.pi * np.sqrt(np.maximum(m2, 1))),
+                     -(h * h / (4 * np.pi)) * 2.837297479480619)
+        out.append(float(np.sum(k * rho)))
+    return np.array(out)
+
+
+def test_full_free256(torch_dev):
+    """The 256^3 free-BC workload (padded 512^3) at full size, in the
+    configuration the benchmark times."""
+    torch = torch_dev
+    n, bc, rho = workload_density("free256")
+    rho32 = rho.astype(np.float32)
+    V, plan = _gpu_solve(torch, n, bc, rho32)
+    ref = oracle.solve(rho32.astype(np.float64), bc, H)
+    err = _check(V, ref, "free256")
+    dev = P.poisson_rel_l2(torch.from_numpy(V).cuda(), torch.from_numpy(ref).cuda(), V.size)
+    assert dev == pytest.approx(err, rel=1e-6)
+    rng = np.random.default_rng(0)
+    pts = [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(6)] + [(0, 0, 0), (255, 255, 255)]
+    direct = _direct_free_samples(rho32.astype(np.float64), H, pts)
+    got = np.array([V[k, j, i] for (i, j, k) in pts], dtype=np.float64)
+    assert np.max(np.abs(got - direct)) <= ELEM * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("name", ["wire192x192x384", "surface384x192x384"])
+def test_full_mixed_bc_large(torch_dev, name):
+    n, bc, rho = workload_density(name)
+    rho32 = rho.astype(np.float32)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho32)
+    _check(V, oracle.solve(rho32.astype(np.float64), bc, H), name)
