@@ -55,6 +55,23 @@ def cpu_baseline(rho32, n, bc, reps=3):
                          f"(scipy.fft, workers={workers}, K^F prebuilt); median {med:.3f} s"}
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=20):
+    """Device-to-device copy rate (read + write bytes / time) of a plain copy."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +79,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="free256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -74,6 +93,9 @@ def main():
     from densities import WORKLOADS, workload_density
 
     dev = torch.device("cuda:0")
+    if args.copy_only:
+        print(json.dumps({"copy_gbs": copy_bandwidth(torch, dev)}), flush=True)
+        return
     P.load_library()
     n, bc, rho = workload_density(args.workload, H)
     rho32 = rho.astype(np.float32)
@@ -109,6 +131,7 @@ def main():
                 for p in range(5)]
 
     V_gpu = V.cpu().numpy()
+    copy_gbs = copy_bandwidth(torch, dev)
     pb = pass_bytes(n, info)
     dom = int(np.argmax(per_pass))
     achieved = pb[dom] / (per_pass[dom] * 1e-3) / 1e9
@@ -136,6 +159,8 @@ def main():
                      "launch_ms": per_pass[dom]},
         "solve_roofline": {"alg_bytes": info["alg_bytes"], "achieved": solve_gbs,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": solve_gbs / HBM_PEAK_GBS},
+        "copy_gbs": copy_gbs,
+        "solve_vs_copy": solve_gbs / copy_gbs,
         "passes_ms": dict(zip(PASS_NAMES, per_pass)),
         "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
     }

@@ -1,22 +1,32 @@
 // passes.hip - the five passes of one solve (paper, Section 3).
 //
-//   P1 R2C    real-to-complex along p of the density, zero-padded half
-//             skipped (spread_X + 1DFFT_X of the paper's step list)
-//   P2 FWD    forward along q (transpose/spread_Y + 1DFFT_Y)
-//   P3 CONV   forward along r, times K^F, inverse along r, crop
-//             (spread_Z + 1DFFT_Z + kernel multiplication + inverse_1DFFT_Z +
-//             compactification_Z, with the kernel stored in pass order so no
-//             final transpose is needed)
-//   P4 INV    inverse along q, crop (compactification_Y + transpose)
-//   P5 C2R    complex-to-real along p, crop (inverse_1DFFT_X +
-//             compactification_X)
+//   P1 r2c   real-to-complex along p of the density, zero-padded half skipped
+//            (spread_X + 1DFFT_X of the paper's step list)
+//   P2 c2c   forward along q (transpose/spread_Y + 1DFFT_Y)
+//   P3 conv  forward along r, times K^F, inverse along r, crop
+//            (spread_Z + 1DFFT_Z + kernel multiplication + inverse_1DFFT_Z +
+//            compactification_Z, with the kernel stored in pass order so no
+//            final transpose is needed)
+//   P4 c2c   inverse along q, crop (compactification_Y + transpose)
+//   P5 c2r   complex-to-real along p, crop (inverse_1DFFT_X +
+//            compactification_X)
 //
-// The paper's separate transpose/spread/compaction kernels do not exist here:
-// zero padding happens in registers at load time, crops at store time, and
-// the transposes are the LDS staging of tiled sides (plan.cpp picks layouts
-// so every pass has at most one strided side per array, read or written as
-// rows of W consecutive lines).  Each HBM array is read and written once
-// per pass.
+// The paper's separate transpose, spread and compaction kernels do not exist
+// here: zero padding happens in registers at load time, crops at store time,
+// and the transposes are the LDS staging of tiled sides (plan.cpp picks
+// layouts so each side of a pass is either one contiguous line per line
+// group or rows of W consecutive lines).  Each HBM array is read and written
+// once per pass.
+//
+// Workgroups are persistent over tiles and prefetch the next tile's input
+// into registers while the current tile is transformed, so the HBM reads of
+// one tile overlap the FFT arithmetic of the previous one.
+//
+// The real passes transform two real lines per complex FFT: P1 packs lines
+// a and b as a + i b and separates X_a[k] = (Z[k] + conj Z[L-k]) / 2,
+// X_b[k] = (Z[k] - conj Z[L-k]) / (2i); P5 forms Z = X_a + i X_b from the two
+// Hermitian halves, so the real part of its inverse is line a and the
+// imaginary part line b.
 #include <hip/hip_runtime.h>
 
 #include "fft_core.h"
@@ -34,107 +44,124 @@ struct PassParams {
   const void *in;
   void *out;
   const float2 *tw;
-  long long in_sl, in_st, in_sb;
-  long long out_sl, out_st, out_sb;
+  int in_sl, in_st, in_sb;  // element strides (line, tile, batch); arrays < 2^31 elements
+  int out_sl, out_st, out_sb;
   int ext_tile;
   int tiles_per_batch;
   int ntiles;
 };
 
-template <int L> struct TileCfg {
+// Workgroup geometry for length L: NW waves of LPW line groups of T lanes.
+template <int L> struct Geo {
   static constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T;
-  static constexpr int NW = LPW >= 16 ? 1 : 16 / LPW;  // waves per workgroup
-  static constexpr int W = NW * LPW;                    // lines per tile
-  static constexpr int NTHREADS = NW * 64;
+  static constexpr int NW = LPW >= 16 ? 1 : 16 / LPW;
+  static constexpr int NT = NW * 64;
+  static constexpr int G = NW * LPW;  // complex lines in flight per workgroup
   static constexpr int SLOTS = line_lds_slots<L>();
-  static constexpr int LD = W + 1;  // row stride of a staged tile (elements)
-  static constexpr int TILE_F2 = (L + 1) * LD;
-  static constexpr int XCH_F2 = W * SLOTS;
-  static constexpr int LDS_F2 = TILE_F2 > XCH_F2 ? TILE_F2 : XCH_F2;
+  static constexpr int XCH_F2 = G * SLOTS;
 };
 
-// KIND: KIND_R2C, KIND_FWD, KIND_INV or KIND_C2R.  PC: pad (R2C/FWD) or
-// crop (INV/C2R) along the line axis.
-template <int L, int KIND, bool IN_TILED, bool OUT_TILED, bool PC>
-__global__ __launch_bounds__(TileCfg<L>::NTHREADS) void pass_kernel(PassParams a) {
-  using C = TileCfg<L>;
-  constexpr int E = C::E, T = C::T, LPW = C::LPW, W = C::W, LD = C::LD, NT = C::NTHREADS;
-  constexpr bool REAL_IN = KIND == KIND_R2C;
-  constexpr bool REAL_OUT = KIND == KIND_C2R;
-  constexpr bool INV = KIND == KIND_INV || KIND == KIND_C2R;
-  constexpr bool PAD = !INV && PC;
-  constexpr bool CROP = INV && PC;
-  constexpr int ROWS_IN = KIND == KIND_C2R ? L / 2 + 1 : (PAD ? L / 2 : L);
-  constexpr int ROWS_OUT = KIND == KIND_R2C ? L / 2 + 1 : (CROP ? L / 2 : L);
+template <int A, int B> constexpr int cmax() { return A > B ? A : B; }
 
-  __shared__ float2 smem[C::LDS_F2];
-  float *smem_f = reinterpret_cast<float *>(smem);
+// A ROWS x W tile moved between HBM (rows at stride `sl`, W consecutive
+// elements per row) and LDS (row stride LD) by all NT threads, through
+// registers so the HBM side can be issued early.
+template <int ROWS, int W, int NT, int LD, typename TE> struct TileRegs {
+  static constexpr int N = ROWS * W, PF = (N + NT - 1) / NT;
+  TE r[PF];
+  __device__ __forceinline__ void load(const TE *__restrict__ base, int sl, int ncols,
+                                       int tid) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int idx = tid + p * NT;
+      const int row = idx / W, col = idx % W;
+      if (idx < N && col < ncols) r[p] = base[row * sl + col];
+    }
+  }
+  __device__ __forceinline__ void to_lds(TE *tile, int tid) const {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int idx = tid + p * NT;
+      if (idx < N) tile[(idx / W) * LD + (idx % W)] = r[p];
+    }
+  }
+};
+
+template <int ROWS, int W, int NT, int LD, typename TE>
+__device__ __forceinline__ void tile_store(TE *__restrict__ base, int sl, int ncols,
+                                           const TE *tile, int tid) {
+  for (int idx = tid; idx < ROWS * W; idx += NT) {
+    const int row = idx / W, col = idx % W;
+    if (col < ncols) base[row * sl + col] = tile[row * LD + col];
+  }
+}
+
+struct TileCoord {
+  int a0, ncols, b;
+};
+
+__device__ __forceinline__ TileCoord tile_coord(const PassParams &a, int tile, int W) {
+  TileCoord c;
+  c.a0 = (tile % a.tiles_per_batch) * W;
+  c.b = tile / a.tiles_per_batch;
+  c.ncols = min(W, a.ext_tile - c.a0);
+  return c;
+}
+
+// ------------------------------------------------------------- P2 / P4
+template <int L, bool INV, bool IN_TILED, bool OUT_TILED, bool PC>
+__global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
+  using C = Geo<L>;
+  constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = C::G, LD = W + 1;
+  constexpr bool PAD = !INV && PC, CROP = INV && PC;
+  constexpr int ROWS_IN = PAD ? L / 2 : L, ROWS_OUT = CROP ? L / 2 : L;
+  constexpr int LDS_F2 = cmax<C::XCH_F2, (L + 1) * LD>();
+  __shared__ float2 smem[LDS_F2];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane / T, t = lane % T;
-  const int c = wave * LPW + g;  // my line within the tile
+  const int c = wave * LPW + g;
   float2 *xch = smem + c * C::SLOTS;
+  const float2 *__restrict__ in = static_cast<const float2 *>(a.in);
+  float2 *__restrict__ out = static_cast<float2 *>(a.out);
 
   Twiddles<L> tw;
   tw.load(a.tw, t);
 
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const int a0 = (tile % a.tiles_per_batch) * W;
-    const long long b = tile / a.tiles_per_batch;
-    const int ncols = min(W, a.ext_tile - a0);
-    const bool valid = c < ncols;
-    float2 v[E];
+  TileRegs<ROWS_IN, W, NT, LD, float2> pf;
+  float2 vn[E];
+  auto fetch = [&](int tile) {
+    const TileCoord q = tile_coord(a, tile, W);
+    if constexpr (IN_TILED) {
+      pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
+    } else {
+      const bool ok = c < q.ncols;
+      const float2 *line = in + (q.a0 + c) * a.in_st + q.b * a.in_sb;
+#pragma unroll
+      for (int i = 0; i < E; ++i)
+        vn[i] = ((!PAD || i < E / 2) && ok) ? line[t + T * i] : make_float2(0.f, 0.f);
+    }
+  };
 
+  int tile = blockIdx.x;
+  if (tile < a.ntiles) fetch(tile);
+  while (tile < a.ntiles) {
+    const TileCoord q = tile_coord(a, tile, W);
+    const int next = tile + gridDim.x;
+    float2 v[E];
     __syncthreads();  // the previous tile is done with smem
     if constexpr (IN_TILED) {
-      // rows of ncols consecutive lines; a.in_st == 1
-      if constexpr (REAL_IN) {
-        const float *in = static_cast<const float *>(a.in) + b * a.in_sb + a0;
-        for (int idx = tid; idx < ROWS_IN * W; idx += NT) {
-          const int row = idx / W, col = idx % W;
-          if (col < ncols) smem_f[row * LD + col] = in[row * a.in_sl + col];
-        }
-      } else {
-        const float2 *in = static_cast<const float2 *>(a.in) + b * a.in_sb + a0;
-        for (int idx = tid; idx < ROWS_IN * W; idx += NT) {
-          const int row = idx / W, col = idx % W;
-          if (col < ncols) smem[row * LD + col] = in[row * a.in_sl + col];
-        }
-      }
+      pf.to_lds(smem, tid);
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        const int k = t + T * i;
-        if constexpr (REAL_IN) {
-          v[i] = (!PAD || i < E / 2) ? make_float2(smem_f[k * LD + c], 0.f) : make_float2(0.f, 0.f);
-        } else if constexpr (KIND == KIND_C2R) {
-          // Hermitian half X[0..L/2]; X[k] = conj(X[L-k]) above L/2
-          if (i < E / 2) {
-            v[i] = smem[k * LD + c];
-          } else {
-            const bool direct = (k == L / 2);
-            const float2 x = smem[(direct ? k : L - k) * LD + c];
-            v[i] = direct ? x : make_float2(x.x, -x.y);
-          }
-        } else {
-          v[i] = (!PAD || i < E / 2) ? smem[k * LD + c] : make_float2(0.f, 0.f);
-        }
-      }
+      for (int i = 0; i < E; ++i)
+        v[i] = (!PAD || i < E / 2) ? smem[(t + T * i) * LD + c] : make_float2(0.f, 0.f);
+      if (next < a.ntiles) fetch(next);
       __syncthreads();  // the tile region becomes exchange space
     } else {
-      // whole lines; a.in_sl == 1
-      const long long base = (long long)(a0 + c) * a.in_st + b * a.in_sb;
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        const int k = t + T * i;
-        if ((!PAD || i < E / 2) && valid) {
-          if constexpr (REAL_IN) v[i] = make_float2(static_cast<const float *>(a.in)[base + k], 0.f);
-          else v[i] = static_cast<const float2 *>(a.in)[base + k];
-        } else {
-          v[i] = make_float2(0.f, 0.f);
-        }
-      }
-      static_assert(KIND != KIND_C2R || IN_TILED, "C2R reads a staged tile");
+      for (int i = 0; i < E; ++i) v[i] = vn[i];
+      if (next < a.ntiles) fetch(next);
     }
 
     fft_line<L, INV>(v, tw, xch, t);
@@ -142,60 +169,214 @@ __global__ __launch_bounds__(TileCfg<L>::NTHREADS) void pass_kernel(PassParams a
     if constexpr (OUT_TILED) {
       __syncthreads();  // every line is done exchanging
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        const int k = t + T * i;
-        bool keep;
-        if constexpr (KIND == KIND_R2C) keep = (i < E / 2) || (i == E / 2 && t == 0);
-        else keep = !CROP || i < E / 2;
-        if (keep) {
-          if constexpr (REAL_OUT) smem_f[k * LD + c] = v[i].x;
-          else smem[k * LD + c] = v[i];
-        }
-      }
+      for (int i = 0; i < E; ++i)
+        if (!CROP || i < E / 2) smem[(t + T * i) * LD + c] = v[i];
       __syncthreads();
-      if constexpr (REAL_OUT) {
-        float *out = static_cast<float *>(a.out) + b * a.out_sb + a0;
-        for (int idx = tid; idx < ROWS_OUT * W; idx += NT) {
-          const int row = idx / W, col = idx % W;
-          if (col < ncols) out[row * a.out_sl + col] = smem_f[row * LD + col];
-        }
-      } else {
-        float2 *out = static_cast<float2 *>(a.out) + b * a.out_sb + a0;
-        for (int idx = tid; idx < ROWS_OUT * W; idx += NT) {
-          const int row = idx / W, col = idx % W;
-          if (col < ncols) out[row * a.out_sl + col] = smem[row * LD + col];
-        }
-      }
+      tile_store<ROWS_OUT, W, NT, LD>(out + q.b * a.out_sb + q.a0, a.out_sl, q.ncols, smem, tid);
     } else {
-      static_assert(KIND != KIND_R2C, "R2C writes a staged tile");
-      if (valid) {
-        const long long base = (long long)(a0 + c) * a.out_st + b * a.out_sb;
+      if (c < q.ncols) {
+        float2 *line = out + (q.a0 + c) * a.out_st + q.b * a.out_sb;
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-          const int k = t + T * i;
-          if (!CROP || i < E / 2) {
-            if constexpr (REAL_OUT) static_cast<float *>(a.out)[base + k] = v[i].x;
-            else static_cast<float2 *>(a.out)[base + k] = v[i];
-          }
-        }
+        for (int i = 0; i < E; ++i)
+          if (!CROP || i < E / 2) line[t + T * i] = v[i];
       }
     }
+    tile = next;
   }
 }
 
-// ---------------------------------------------------------------- P3
+// ------------------------------------------------------------------ P1
+template <int L, bool IN_TILED, bool PAD>
+__global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
+  using C = Geo<L>;
+  constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = 2 * C::G;
+  constexpr int LDR = W + 2, LDC = W + 1;  // real tile (floats), complex tile (float2)
+  constexpr int ROWS_IN = PAD ? L / 2 : L, ROWS_OUT = L / 2 + 1;
+  constexpr int LDS_F2 = cmax<cmax<C::XCH_F2, ROWS_OUT * LDC>(), (ROWS_IN * LDR + 1) / 2>();
+  __shared__ float2 smem[LDS_F2];
+  float *smem_f = reinterpret_cast<float *>(smem);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane / T, t = lane % T;
+  const int c = wave * LPW + g;  // complex line: real lines 2c, 2c + 1
+  float2 *xch = smem + c * C::SLOTS;
+  const float *__restrict__ in = static_cast<const float *>(a.in);
+  float2 *__restrict__ out = static_cast<float2 *>(a.out);
+
+  Twiddles<L> tw;
+  tw.load(a.tw, t);
+
+  TileRegs<ROWS_IN, W, NT, LDR, float> pf;
+  float2 vn[E];
+  auto fetch = [&](int tile) {
+    const TileCoord q = tile_coord(a, tile, W);
+    if constexpr (IN_TILED) {
+      pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
+    } else {
+      const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
+      const float *l0 = in + (q.a0 + 2 * c) * a.in_st + q.b * a.in_sb;
+      const float *l1 = l0 + a.in_st;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const bool live = !PAD || i < E / 2;
+        vn[i].x = (live && ok0) ? l0[t + T * i] : 0.f;
+        vn[i].y = (live && ok1) ? l1[t + T * i] : 0.f;
+      }
+    }
+  };
+
+  int tile = blockIdx.x;
+  if (tile < a.ntiles) fetch(tile);
+  while (tile < a.ntiles) {
+    const TileCoord q = tile_coord(a, tile, W);
+    const int next = tile + gridDim.x;
+    float2 v[E];
+    __syncthreads();
+    if constexpr (IN_TILED) {
+      pf.to_lds(smem_f, tid);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < E; ++i)
+        v[i] = (!PAD || i < E / 2)
+                   ? *reinterpret_cast<const float2 *>(smem_f + (t + T * i) * LDR + 2 * c)
+                   : make_float2(0.f, 0.f);
+      if (next < a.ntiles) fetch(next);
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = vn[i];
+      if (next < a.ntiles) fetch(next);
+    }
+
+    fft_line<L, false>(v, tw, xch, t);
+
+    // separate the two real lines: needs Z[L - k] from the mirrored lane
+#pragma unroll
+    for (int i = 0; i < E; ++i) xch[lds_pad(t + T * i)] = v[i];
+    wave_lds_fence();
+    float2 x0[E / 2 + 1], x1[E / 2 + 1];
+#pragma unroll
+    for (int i = 0; i <= E / 2; ++i) {
+      const int k = t + T * i;
+      const int km = (k == 0) ? 0 : L - k;
+      const float2 z = v[i];
+      const float2 zr = xch[lds_pad(km < L ? km : 0)];
+      x0[i] = make_float2(0.5f * (z.x + zr.x), 0.5f * (z.y - zr.y));
+      x1[i] = make_float2(0.5f * (z.y + zr.y), 0.5f * (zr.x - z.x));
+    }
+    __syncthreads();  // every line is done with its exchange region
+#pragma unroll
+    for (int i = 0; i <= E / 2; ++i) {
+      const int k = t + T * i;
+      if (i < E / 2 || t == 0) {
+        smem[k * LDC + 2 * c] = x0[i];
+        smem[k * LDC + 2 * c + 1] = x1[i];
+      }
+    }
+    __syncthreads();
+    tile_store<ROWS_OUT, W, NT, LDC>(out + q.b * a.out_sb + q.a0, a.out_sl, q.ncols, smem, tid);
+    tile = next;
+  }
+}
+
+// ------------------------------------------------------------------ P5
+template <int L, bool OUT_TILED, bool CROP>
+__global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
+  using C = Geo<L>;
+  constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = 2 * C::G;
+  constexpr int LDR = W + 2, LDC = W + 1;
+  constexpr int ROWS_IN = L / 2 + 1, ROWS_OUT = CROP ? L / 2 : L;
+  constexpr int LDS_F2 = cmax<cmax<C::XCH_F2, ROWS_IN * LDC>(), (ROWS_OUT * LDR + 1) / 2>();
+  __shared__ float2 smem[LDS_F2];
+  float *smem_f = reinterpret_cast<float *>(smem);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane / T, t = lane % T;
+  const int c = wave * LPW + g;
+  float2 *xch = smem + c * C::SLOTS;
+  const float2 *__restrict__ in = static_cast<const float2 *>(a.in);
+  float *__restrict__ out = static_cast<float *>(a.out);
+
+  Twiddles<L> tw;
+  tw.load(a.tw, t);
+
+  TileRegs<ROWS_IN, W, NT, LDC, float2> pf;
+  int tile = blockIdx.x;
+  if (tile < a.ntiles) {
+    const TileCoord q = tile_coord(a, tile, W);
+    pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
+  }
+  while (tile < a.ntiles) {
+    const TileCoord q = tile_coord(a, tile, W);
+    const int next = tile + gridDim.x;
+    float2 v[E];
+    __syncthreads();
+    pf.to_lds(smem, tid);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int k = t + T * i;
+      const bool direct = i < E / 2 || k == L / 2;
+      const int kk = direct ? k : L - k;
+      float2 x0 = smem[kk * LDC + 2 * c], x1 = smem[kk * LDC + 2 * c + 1];
+      if (kk == 0 || kk == L / 2) {
+        // DC and Nyquist coefficients of a real line are real
+        x0.y = 0.f;
+        x1.y = 0.f;
+      }
+      // Z = X_a + i X_b, using X[k] = conj(X[L - k]) above L/2
+      v[i] = direct ? make_float2(x0.x - x1.y, x0.y + x1.x) : make_float2(x0.x + x1.y, x1.x - x0.y);
+    }
+    if (next < a.ntiles) {
+      const TileCoord qn = tile_coord(a, next, W);
+      pf.load(in + qn.b * a.in_sb + qn.a0, a.in_sl, qn.ncols, tid);
+    }
+    __syncthreads();
+
+    fft_line<L, true>(v, tw, xch, t);
+
+    if constexpr (OUT_TILED) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < E; ++i)
+        if (!CROP || i < E / 2)
+          *reinterpret_cast<float2 *>(smem_f + (t + T * i) * LDR + 2 * c) = v[i];
+      __syncthreads();
+      tile_store<ROWS_OUT, W, NT, LDR>(out + q.b * a.out_sb + q.a0, a.out_sl, q.ncols, smem_f, tid);
+    } else {
+      const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
+      float *l0 = out + (q.a0 + 2 * c) * a.out_st + q.b * a.out_sb;
+      float *l1 = l0 + a.out_st;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        if (!CROP || i < E / 2) {
+          if (ok0) l0[t + T * i] = v[i].x;
+          if (ok1) l1[t + T * i] = v[i].y;
+        }
+      }
+    }
+    tile = next;
+  }
+}
+
+// ------------------------------------------------------------------ P3
 struct ConvParams {
   float2 *data;       // A2, lines along r contiguous
   const float *kf;    // [k_p][k_q'][k_r'] float32, 1/(S1 S2 S3) folded in
   const float2 *tw;
-  long long st_q, st_p;  // element strides of line (k_p, k_q)
+  int st_q, st_p;     // element strides of line (k_p, k_q)
   int S_q;
   int kq_half;        // S_q/2 + 1
-  long long nrows;    // H * kq_half kernel rows
+  int H;              // number of k_p planes
+  int nrows;          // H * kq_half kernel rows
 };
 
 constexpr int kConvWaves = 4;
 
+// One kernel row (k_p, k_q') serves the lines k_q = k_q' and S_q - k_q'
+// (K^F is even in k_q); the mirror line re-reads the row from cache.  Each
+// line group walks its rows in order with two line buffers: the next line
+// (and its kernel values) is loaded while the current one is transformed.
 template <int L, bool PC>
 __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T, KR = L / 2 + 1;
@@ -205,39 +386,73 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   const int g = lane / T, t = lane % T;
   float2 *xch = smem + (wave * LPW + g) * SLOTS;
 
+  const int row0 = (blockIdx.x * kConvWaves + wave) * LPW + g;
+  if (row0 >= a.nrows) return;  // no barriers below: groups run independently
+
   Twiddles<L> tw;
   tw.load(a.tw, t);
 
-  const long long ngroups = (long long)gridDim.x * kConvWaves * LPW;
-  // One kernel row (k_p, k_q') serves the lines k_q = k_q' and S_q - k_q':
-  // K^F is even in k_q, so the row is read from HBM once for both.
-  for (long long row = ((long long)blockIdx.x * kConvWaves + wave) * LPW + g; row < a.nrows;
-       row += ngroups) {
-    const int kp = int(row / a.kq_half);
-    const int kqf = int(row % a.kq_half);
-    float kv[E];
-    const float *krow = a.kf + row * KR;
+  const int stride = gridDim.x * kConvWaves * LPW;
+  const int dkp = stride / a.kq_half, dkq = stride % a.kq_half;
+  int kp = row0 / a.kq_half, kqf = row0 % a.kq_half, rep = 0;
+
+  struct Item {
+    float2 v[E];
+    float k[E];
+    int off;
+    bool live;
+  };
+  auto fetch = [&](Item &it) {
+    it.live = kp < a.H;
+    if (!it.live) return;
+    const int kq = rep == 0 ? kqf : a.S_q - kqf;
+    it.off = kp * a.st_p + kq * a.st_q;
+    const float2 *line = a.data + it.off;
+    const float *krow = a.kf + (kp * a.kq_half + kqf) * KR;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int k = t + T * i;
-      kv[i] = krow[k <= L / 2 ? k : L - k];
+      it.v[i] = (!PC || i < E / 2) ? line[k] : make_float2(0.f, 0.f);
+      it.k[i] = krow[k <= L / 2 ? k : L - k];
     }
-    const int nrep = (kqf == 0 || 2 * kqf == a.S_q) ? 1 : 2;
-    for (int rep = 0; rep < nrep; ++rep) {
-      const int kq = rep == 0 ? kqf : a.S_q - kqf;
-      float2 *line = a.data + kp * a.st_p + kq * a.st_q;
-      float2 v[E];
-#pragma unroll
-      for (int i = 0; i < E; ++i)
-        v[i] = (!PC || i < E / 2) ? line[t + T * i] : make_float2(0.f, 0.f);
-      fft_line<L, false>(v, tw, xch, t);
-#pragma unroll
-      for (int i = 0; i < E; ++i) v[i] = make_float2(v[i].x * kv[i], v[i].y * kv[i]);
-      fft_line<L, true>(v, tw, xch, t);
-#pragma unroll
-      for (int i = 0; i < E; ++i)
-        if (!PC || i < E / 2) line[t + T * i] = v[i];
+  };
+  auto advance = [&]() {
+    const bool pair = kqf != 0 && 2 * kqf != a.S_q;
+    if (rep == 0 && pair) {
+      rep = 1;
+    } else {
+      rep = 0;
+      kqf += dkq;
+      kp += dkp;
+      if (kqf >= a.kq_half) {
+        kqf -= a.kq_half;
+        ++kp;
+      }
     }
+  };
+  auto process = [&](Item &it) {
+    fft_line<L, false>(it.v, tw, xch, t);
+#pragma unroll
+    for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
+    fft_line<L, true>(it.v, tw, xch, t);
+    float2 *line = a.data + it.off;
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      if (!PC || i < E / 2) line[t + T * i] = it.v[i];
+  };
+
+  Item A, B;
+  fetch(A);
+  advance();
+  while (true) {
+    fetch(B);
+    advance();
+    process(A);
+    if (!B.live) break;
+    fetch(A);
+    advance();
+    process(B);
+    if (!A.live) break;
   }
 }
 
@@ -256,30 +471,64 @@ int device_cu_count() {
   return cus;
 }
 
-template <int L, int KIND, bool IT, bool OT, bool PC>
-hipError_t launch_tiled(const Pass &P, const void *in, void *out, const float2 *tw,
-                        hipStream_t s) {
-  using C = TileCfg<L>;
+PassParams make_params(const Pass &P, const void *in, void *out, const float2 *tw, int W) {
   PassParams a;
   a.in = in;
   a.out = out;
   a.tw = tw;
-  a.in_sl = P.in_s[0];
-  a.in_st = P.in_s[1];
-  a.in_sb = P.in_s[2];
-  a.out_sl = P.out_s[0];
-  a.out_st = P.out_s[1];
-  a.out_sb = P.out_s[2];
+  a.in_sl = int(P.in_s[0]);
+  a.in_st = int(P.in_s[1]);
+  a.in_sb = int(P.in_s[2]);
+  a.out_sl = int(P.out_s[0]);
+  a.out_st = int(P.out_s[1]);
+  a.out_sb = int(P.out_s[2]);
   a.ext_tile = P.ext_tile;
-  a.tiles_per_batch = (P.ext_tile + C::W - 1) / C::W;
-  const long long nt = (long long)a.tiles_per_batch * P.ext_batch;
-  a.ntiles = int(nt);
-  const int lds_bytes = C::LDS_F2 * 8;
-  const int per_cu = lds_bytes > 0 ? (160 * 1024) / lds_bytes : 8;
-  const long long cap = (long long)device_cu_count() * (per_cu > 0 ? per_cu : 1) * 4;
-  const int grid = int(nt < cap ? nt : cap);
+  a.tiles_per_batch = (P.ext_tile + W - 1) / W;
+  a.ntiles = a.tiles_per_batch * P.ext_batch;
+  return a;
+}
+
+// persistent grid: as many workgroups as fit on the device at once
+template <typename K>
+int persistent_grid(K kernel, int threads, int ntiles) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  const long long cap = (long long)device_cu_count() * per_cu;
+  return int(ntiles < cap ? ntiles : cap);
+}
+
+template <int L, bool INV, bool IT, bool OT, bool PC>
+hipError_t launch_c2c(const Pass &P, const void *in, void *out, const float2 *tw, hipStream_t s) {
+  using C = Geo<L>;
+  PassParams a = make_params(P, in, out, tw, C::G);
+  auto k = c2c_kernel<L, INV, IT, OT, PC>;
+  const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((pass_kernel<L, KIND, IT, OT, PC>), dim3(grid), dim3(C::NTHREADS), 0, s, a);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int L, bool IT, bool PAD>
+hipError_t launch_r2c(const Pass &P, const void *in, void *out, const float2 *tw, hipStream_t s) {
+  using C = Geo<L>;
+  PassParams a = make_params(P, in, out, tw, 2 * C::G);
+  auto k = r2c_kernel<L, IT, PAD>;
+  const int grid = persistent_grid(k, C::NT, a.ntiles);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int L, bool OT, bool CROP>
+hipError_t launch_c2r(const Pass &P, const void *in, void *out, const float2 *tw, hipStream_t s) {
+  using C = Geo<L>;
+  PassParams a = make_params(P, in, out, tw, 2 * C::G);
+  auto k = c2r_kernel<L, OT, CROP>;
+  const int grid = persistent_grid(k, C::NT, a.ntiles);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -290,18 +539,19 @@ hipError_t launch_conv(const Pass &P, void *data, const float2 *tw, const float 
   a.data = static_cast<float2 *>(data);
   a.kf = kf;
   a.tw = tw;
-  a.st_q = P.in_s[1];
-  a.st_p = P.in_s[2];
+  a.st_q = int(P.in_s[1]);
+  a.st_p = int(P.in_s[2]);
   a.S_q = S_q;
   a.kq_half = S_q / 2 + 1;
-  a.nrows = (long long)P.ext_batch * a.kq_half;
+  a.H = P.ext_batch;
+  a.nrows = P.ext_batch * a.kq_half;
   constexpr int LPW = 64 / (L / Shape<L>::E);
   const long long groups_per_block = (long long)kConvWaves * LPW;
-  long long blocks = (a.nrows + groups_per_block - 1) / groups_per_block;
-  const long long cap = (long long)device_cu_count() * 8;
-  if (blocks > cap) blocks = cap;
+  const long long need = (a.nrows + groups_per_block - 1) / groups_per_block;
+  auto k = conv_kernel<L, PC>;
+  const int blocks = persistent_grid(k, kConvWaves * 64, int(need < (1 << 30) ? need : (1 << 30)));
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((conv_kernel<L, PC>), dim3(int(blocks)), dim3(kConvWaves * 64), 0, s, a);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(kConvWaves * 64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -313,28 +563,28 @@ hipError_t launch_for_length(const Pass &P, const void *in, void *out, const flo
   const bool it = P.in_tiled, ot = P.out_tiled;
   switch (P.kind) {
     case KIND_R2C:
-      if (it) return P.pad ? launch_tiled<L, KIND_R2C, true, true, true>(P, in, out, tw, s)
-                           : launch_tiled<L, KIND_R2C, true, true, false>(P, in, out, tw, s);
-      return P.pad ? launch_tiled<L, KIND_R2C, false, true, true>(P, in, out, tw, s)
-                   : launch_tiled<L, KIND_R2C, false, true, false>(P, in, out, tw, s);
+      if (it) return P.pad ? launch_r2c<L, true, true>(P, in, out, tw, s)
+                           : launch_r2c<L, true, false>(P, in, out, tw, s);
+      return P.pad ? launch_r2c<L, false, true>(P, in, out, tw, s)
+                   : launch_r2c<L, false, false>(P, in, out, tw, s);
     case KIND_FWD:
-      if (it) return P.pad ? launch_tiled<L, KIND_FWD, true, true, true>(P, in, out, tw, s)
-                           : launch_tiled<L, KIND_FWD, true, true, false>(P, in, out, tw, s);
-      return P.pad ? launch_tiled<L, KIND_FWD, false, true, true>(P, in, out, tw, s)
-                   : launch_tiled<L, KIND_FWD, false, true, false>(P, in, out, tw, s);
+      if (it) return P.pad ? launch_c2c<L, false, true, true, true>(P, in, out, tw, s)
+                           : launch_c2c<L, false, true, true, false>(P, in, out, tw, s);
+      return P.pad ? launch_c2c<L, false, false, true, true>(P, in, out, tw, s)
+                   : launch_c2c<L, false, false, true, false>(P, in, out, tw, s);
     case KIND_CONV:
       return P.pad ? launch_conv<L, true>(P, out, tw, kf, S_q, s)
                    : launch_conv<L, false>(P, out, tw, kf, S_q, s);
     case KIND_INV:
-      if (ot) return P.crop ? launch_tiled<L, KIND_INV, true, true, true>(P, in, out, tw, s)
-                            : launch_tiled<L, KIND_INV, true, true, false>(P, in, out, tw, s);
-      return P.crop ? launch_tiled<L, KIND_INV, true, false, true>(P, in, out, tw, s)
-                    : launch_tiled<L, KIND_INV, true, false, false>(P, in, out, tw, s);
+      if (ot) return P.crop ? launch_c2c<L, true, true, true, true>(P, in, out, tw, s)
+                            : launch_c2c<L, true, true, true, false>(P, in, out, tw, s);
+      return P.crop ? launch_c2c<L, true, true, false, true>(P, in, out, tw, s)
+                    : launch_c2c<L, true, true, false, false>(P, in, out, tw, s);
     case KIND_C2R:
-      if (ot) return P.crop ? launch_tiled<L, KIND_C2R, true, true, true>(P, in, out, tw, s)
-                            : launch_tiled<L, KIND_C2R, true, true, false>(P, in, out, tw, s);
-      return P.crop ? launch_tiled<L, KIND_C2R, true, false, true>(P, in, out, tw, s)
-                    : launch_tiled<L, KIND_C2R, true, false, false>(P, in, out, tw, s);
+      if (ot) return P.crop ? launch_c2r<L, true, true>(P, in, out, tw, s)
+                            : launch_c2r<L, true, false>(P, in, out, tw, s);
+      return P.crop ? launch_c2r<L, false, true>(P, in, out, tw, s)
+                    : launch_c2r<L, false, false>(P, in, out, tw, s);
   }
   return hipErrorInvalidValue;
 }
