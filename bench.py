@@ -37,6 +37,28 @@ def pass_bytes(n, info):
     return [4 * grid + a1, a1 + a2, 2 * a2 + kf, a2 + a1, a1 + 4 * grid]
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in ("paper_1211_5244_amd/csrc/passes.hip", "paper_1211_5244_amd/csrc/fft_core.h"):
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    path = os.path.join(root, "profiles", "pmc_traffic_free256.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel:
+            fields = dict(p.split("=", 1) for p in parts[2:])
+            if fields.get("source_sha") == sha:
+                return float(fields["bytes"])
+    return None
+
+
 def cpu_baseline(rho32, n, bc, reps=3):
     """The FP64 oracle on this host, K^F prebuilt (as the GPU's is)."""
     import oracle
@@ -155,7 +177,9 @@ def main():
                    "gaussians": WORKLOADS[args.workload]["gaussians"], "precision": "fp32"},
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": pb[dom],
+                     "traffic": (measured_traffic(PASS_NAMES[dom]) if args.workload == "free256"
+                                 else None),
+                     "alg_bytes_per_launch": pb[dom],
                      "launch_ms": per_pass[dom]},
         "solve_roofline": {"alg_bytes": info["alg_bytes"], "achieved": solve_gbs,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": solve_gbs / HBM_PEAK_GBS},
