@@ -94,6 +94,63 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+def bench_batch(torch, P, dev, reps=5):
+    """512 mixed solves: a per-solve loop of poisson_solve, the grouped batch
+    (poisson_batch_solve) and the same batch replayed from a HIP graph."""
+    from densities import batch_density, batch_workload
+    items = batch_workload(512)
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).to(dev)
+            for n, bc, seed in items]
+    Vs = [torch.empty_like(r) for r in rhos]
+    alg = sum(P.poisson_plan_describe(*n, bc)["alg_bytes"] for n, bc, _ in items)
+    stream = torch.cuda.current_stream(dev)
+    plans = {}
+    for n, bc, _ in items:
+        if (n, bc) not in plans:
+            plans[(n, bc)] = P.Plan(n, bc, H)
+    B = P.Batch([it[0] for it in items], [it[1] for it in items], [H] * len(items))
+    torch.cuda.synchronize()
+
+    def loop():
+        for (n, bc, _), r, v in zip(items, rhos, Vs):
+            P.poisson_solve(plans[(n, bc)].handle, r, v, stream)
+
+    def batched():
+        P.poisson_batch_solve(B.handle, rhos, Vs, stream)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_loop = timed(loop)
+    ref = [v.clone() for v in Vs]
+    t_batch = timed(batched)
+    same = all(torch.equal(a, b) for a, b in zip(ref, Vs))
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream(dev))
+    torch.cuda.synchronize()
+    t_graph = timed(g.replay)
+    same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
+    out = {"workload": "batch512 (edges 32..128, 4 BC classes, 4 Gaussians)", "solves": len(items),
+           "alg_bytes": alg, "identical_results": bool(same)}
+    for name, t in (("fp32_loop", t_loop), ("fp32_batched", t_batch), ("fp32_batched_graph", t_graph)):
+        out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),
+                     "alg_gbs": alg / (t * 1e-3) / 1e9}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +158,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="free256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-solve batch")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +246,8 @@ def main():
         "passes_ms": dict(zip(PASS_NAMES, per_pass)),
         "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
     }
+    if not args.no_batch:
+        out["batch"] = bench_batch(torch, P, dev)
     if not args.no_cpu_baseline:
         V_ref, cb = cpu_baseline(rho32, n, bc)
         out["cpu_baseline"] = cb

@@ -1,7 +1,9 @@
 // api.cpp - the C ABI of libpoisson (declared in include/poisson.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -67,12 +69,17 @@ struct poisson_plan_s {
   float *kf32 = nullptr;
   void *ws = nullptr;
   bool own_ws = false;
+  bool auto_ws = true;  // allocate a workspace when the kernel is set
   bool kernel_ready = false;
 };
 
 struct poisson_batch_s {
-  std::vector<poisson_plan_t> plans;  // unique problems
-  std::vector<int> which;             // solve i uses plans[which[i]]
+  std::vector<poisson_plan_t> plans;        // unique problems
+  std::vector<int> which;                   // solve i uses plans[which[i]]
+  std::vector<std::vector<int>> members;    // per plan: its solves, in order
+  std::vector<int> chunk;                   // per plan: solves per launch
+  void *ws = nullptr;                       // shared by all chunks (one stream)
+  size_t ws_bytes = 0;
   int device = 0;
 };
 
@@ -103,7 +110,7 @@ void plan_free_all(poisson_plan_t P) {
 }
 
 int ensure_workspace(poisson_plan_t P) {
-  if (P->ws) return POISSON_OK;
+  if (P->ws || !P->auto_ws) return POISSON_OK;
   void *p = nullptr;
   int rc = plan_alloc(P, &p, P->g.ws_bytes, "hipMalloc(workspace)");
   if (rc) return rc;
@@ -316,6 +323,45 @@ int poisson_kernel_get(poisson_plan_t P, double *host) {
   return POISSON_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Enqueue passes first..last for `count` solves of plan P whose
+// intermediates live in `ws`: count A1 arrays, then count A2 arrays.
+int enqueue_passes(poisson_plan_t P, int count, const float *const *rho, float *const *V,
+                   void *ws, int first, int last, hipStream_t s) {
+  const Geometry &g = P->g;
+  char *base = static_cast<char *>(ws);
+  char *a1 = base;
+  char *a2 = base + size_t(count) * g.a1_bytes;
+  const int p = g.order[0], q = g.order[1], r = g.order[2];
+  const float2 *tws[5] = {P->tw[p], P->tw[q], P->tw[r], P->tw[q], P->tw[p]};
+  for (int k = first; k <= last; ++k) {
+    psn::PassIO io;
+    io.count = count;
+    io.conv_stride = (long long)(g.a2_bytes / sizeof(float2));
+    for (int j = 0; j < count; ++j) {
+      void *A1 = a1 + size_t(j) * g.a1_bytes;
+      void *A2 = a2 + size_t(j) * g.a2_bytes;
+      switch (k) {
+        case 0: io.in[j] = rho[j]; io.out[j] = A1; break;
+        case 1: io.in[j] = A1; io.out[j] = A2; break;
+        case 2: io.in[j] = A2; io.out[j] = A2; break;
+        case 3: io.in[j] = A2; io.out[j] = A1; break;
+        default: io.in[j] = A1; io.out[j] = V[j]; break;
+      }
+    }
+    hipError_t e = psn::launch_pass(g.pass[k], io, tws[k], P->kf32, g.S[q], s);
+    if (e != hipSuccess) return hip_fail(e, "pass launch");
+  }
+  return POISSON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int poisson_solve(poisson_plan_t P, const float *rho, float *V, void *stream) {
   return poisson_solve_passes(P, rho, V, 0, 4, stream);
 }
@@ -330,23 +376,7 @@ int poisson_solve_passes(poisson_plan_t P, const float *rho, float *V, int first
   DeviceScope ds(P->device);
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Geometry &g = P->g;
-  char *ws = static_cast<char *>(P->ws);
-  float2 *A1 = reinterpret_cast<float2 *>(ws);
-  float2 *A2 = reinterpret_cast<float2 *>(ws + g.a1_bytes);
-  const int p = g.order[0], q = g.order[1], r = g.order[2];
-  const int Sq = g.S[q];
-  struct Step {
-    const void *in;
-    void *out;
-    const float2 *tw;
-  } steps[5] = {{rho, A1, P->tw[p]}, {A1, A2, P->tw[q]}, {A2, A2, P->tw[r]},
-                {A2, A1, P->tw[q]}, {A1, V, P->tw[p]}};
-  for (int k = first; k <= last; ++k) {
-    hipError_t e = psn::launch_pass(g.pass[k], steps[k].in, steps[k].out, steps[k].tw, P->kf32, Sq, s);
-    if (e != hipSuccess) return hip_fail(e, "pass launch");
-  }
-  return POISSON_OK;
+  return enqueue_passes(P, 1, &rho, &V, P->ws, first, last, s);
 }
 
 int poisson_plan_destroy(poisson_plan_t P) {
@@ -379,6 +409,13 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n, const un
     }
     poisson_batch_t B = new (std::nothrow) poisson_batch_s();
     if (!B) return fail(POISSON_E_NOMEM, "host allocation failed");
+    auto cleanup = [&](int code) {
+      std::string msg = g_last_error;
+      for (auto *pp : B->plans) poisson_plan_destroy(pp);
+      if (B->ws) (void)hipFree(B->ws);
+      delete B;
+      return fail(code, msg);
+    };
     (void)hipGetDevice(&B->device);
     std::map<std::tuple<int, int, int, unsigned, double>, int> index;
     for (int i = 0; i < count; ++i) {
@@ -387,16 +424,41 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n, const un
       if (it == index.end()) {
         poisson_plan_t P = nullptr;
         rc = poisson_plan(&P, n[3 * i], n[3 * i + 1], n[3 * i + 2], bc_mask[i], h[i], precision);
-        if (rc) {
-          std::string msg = g_last_error;
-          for (auto *pp : B->plans) poisson_plan_destroy(pp);
-          delete B;
-          return fail(rc, msg);
-        }
+        if (rc) return cleanup(rc);
+        P->auto_ws = false;  // the batch owns one workspace for every chunk
         it = index.emplace(key, int(B->plans.size())).first;
         B->plans.push_back(P);
+        B->members.emplace_back();
       }
       B->which.push_back(it->second);
+      B->members[it->second].push_back(i);
+    }
+    // Solves per launch: as many as keep a chunk's intermediates within the
+    // budget (default 96 MiB, below the 256 MB Infinity Cache, so the five
+    // passes of a chunk re-read their intermediates from cache), at most
+    // kMaxBatch.
+    double budget_mb = 96.0;
+    if (const char *env = std::getenv("POISSON_BATCH_CHUNK_MB")) {
+      const double v = std::atof(env);
+      if (v > 0) budget_mb = v;
+    }
+    const size_t budget = size_t(budget_mb * 1024.0 * 1024.0);
+    for (size_t u = 0; u < B->plans.size(); ++u) {
+      const size_t per = B->plans[u]->g.ws_bytes;
+      size_t c = per > 0 ? budget / per : 1;
+      if (c < 1) c = 1;
+      if (c > size_t(psn::kMaxBatch)) c = psn::kMaxBatch;
+      if (c > B->members[u].size()) c = B->members[u].size();
+      B->chunk.push_back(int(c));
+      const size_t need = c * per;
+      if (need > B->ws_bytes) B->ws_bytes = need;
+    }
+    hipError_t e = hipMalloc(&B->ws, B->ws_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      B->ws = nullptr;
+      hip_fail(e, "hipMalloc(batch workspace)");
+      return cleanup(e == hipErrorOutOfMemory ? POISSON_E_NOMEM : POISSON_E_HIP);
     }
     *out = B;
     return POISSON_OK;
@@ -420,15 +482,34 @@ int poisson_batch_solve(poisson_batch_t B, const float *const *rho, float *const
     if (!rho[i] || !V[i]) return fail(POISSON_E_ARG, "batch entry " + std::to_string(i) + ": NULL pointer");
   for (auto *P : B->plans)
     if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "batch kernels not built");
-  for (size_t i = 0; i < B->which.size(); ++i) {
-    int rc = poisson_solve(B->plans[B->which[i]], rho[i], V[i], stream);
-    if (rc) return rc;
+  DeviceScope ds(B->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the batch's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<const float *> r(psn::kMaxBatch);
+  std::vector<float *> v(psn::kMaxBatch);
+  for (size_t u = 0; u < B->plans.size(); ++u) {
+    const std::vector<int> &m = B->members[u];
+    const int c = B->chunk[u];
+    for (size_t start = 0; start < m.size(); start += size_t(c)) {
+      const int cnt = int(std::min(m.size() - start, size_t(c)));
+      for (int j = 0; j < cnt; ++j) {
+        r[j] = rho[m[start + j]];
+        v[j] = V[m[start + j]];
+      }
+      int rc = enqueue_passes(B->plans[u], cnt, r.data(), v.data(), B->ws, 0, 4, s);
+      if (rc) return rc;
+    }
   }
   return POISSON_OK;
 }
 
 int poisson_batch_destroy(poisson_batch_t B) {
   if (!B) return POISSON_OK;
+  {
+    DeviceScope ds(B->device);
+    (void)hipDeviceSynchronize();
+    if (B->ws) (void)hipFree(B->ws);
+  }
   for (auto *P : B->plans) poisson_plan_destroy(P);
   delete B;
   return POISSON_OK;

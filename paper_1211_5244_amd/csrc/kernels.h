@@ -7,12 +7,25 @@
 
 namespace psn {
 
-// One pass of the solve on `stream`: reads `in`, writes `out` (complex
-// intermediates are float2, the density and potential float).  `tw` is the
-// table exp(-2 pi i n / L), n = 0..L-1, of the pass's length; `kf` is the
+// Most solves one pass launch covers (their array bases travel as kernel
+// arguments).
+constexpr int kMaxBatch = 64;
+
+// Arrays of the solves one launch covers, all of the same geometry.
+struct PassIO {
+  int count = 0;                    // 1..kMaxBatch
+  const void *in[kMaxBatch] = {};   // per-solve input array
+  void *out[kMaxBatch] = {};        // per-solve output array
+  long long conv_stride = 0;        // conv pass: elements between the A2 arrays of
+                                    // consecutive solves (out[0] is the first)
+};
+
+// One pass on `stream` for io.count solves: reads io.in[j], writes io.out[j]
+// (complex intermediates are float2, density and potential float).  `tw` is
+// the table exp(-2 pi i n / L), n = 0..L-1, of the pass's length; `kf` the
 // float32 K^F in pass order (conv pass only).  Returns a hipError_t.
-hipError_t launch_pass(const Pass &P, const void *in, void *out, const float2 *tw,
-                       const float *kf, int S_q, hipStream_t stream);
+hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                       int S_q, hipStream_t stream);
 
 // float64 K^F octant of the default Green's function (layout of the C ABI:
 // k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.

@@ -35,19 +35,23 @@
 namespace psn {
 
 template <int L>
-hipError_t launch_for_length(const Pass &P, const void *in, void *out, const float2 *tw,
-                             const float *kf, int S_q, hipStream_t s);
+hipError_t launch_for_length(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                             int S_q, hipStream_t s);
 
 #if !defined(PSN_DISPATCH_ONLY)
 
+// One launch covers `nsolve` solves of identical geometry; the tile index
+// runs over solves first-major.  Per-solve array bases are kernel arguments
+// (graph-capturable, no device-side pointer tables).
 struct PassParams {
-  const void *in;
-  void *out;
+  const void *in[kMaxBatch];
+  void *out[kMaxBatch];
   const float2 *tw;
   int in_sl, in_st, in_sb;  // element strides (line, tile, batch); arrays < 2^31 elements
   int out_sl, out_st, out_sb;
   int ext_tile;
   int tiles_per_batch;
+  int tiles_per_solve;
   int ntiles;
 };
 
@@ -97,13 +101,15 @@ __device__ __forceinline__ void tile_store(TE *__restrict__ base, int sl, int nc
 }
 
 struct TileCoord {
-  int a0, ncols, b;
+  int a0, ncols, b, solve;
 };
 
 __device__ __forceinline__ TileCoord tile_coord(const PassParams &a, int tile, int W) {
   TileCoord c;
-  c.a0 = (tile % a.tiles_per_batch) * W;
-  c.b = tile / a.tiles_per_batch;
+  c.solve = tile / a.tiles_per_solve;
+  const int rem = tile - c.solve * a.tiles_per_solve;
+  c.a0 = (rem % a.tiles_per_batch) * W;
+  c.b = rem / a.tiles_per_batch;
   c.ncols = min(W, a.ext_tile - c.a0);
   return c;
 }
@@ -122,8 +128,6 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
   const int g = lane / T, t = lane % T;
   const int c = wave * LPW + g;
   float2 *xch = smem + c * C::SLOTS;
-  const float2 *__restrict__ in = static_cast<const float2 *>(a.in);
-  float2 *__restrict__ out = static_cast<float2 *>(a.out);
 
   Twiddles<L> tw;
   tw.load(a.tw, t);
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
   float2 vn[E];
   auto fetch = [&](int tile) {
     const TileCoord q = tile_coord(a, tile, W);
+    const float2 *__restrict__ in = static_cast<const float2 *>(a.in[q.solve]);
     if constexpr (IN_TILED) {
       pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
     } else {
@@ -172,10 +177,11 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
       for (int i = 0; i < E; ++i)
         if (!CROP || i < E / 2) smem[(t + T * i) * LD + c] = v[i];
       __syncthreads();
-      tile_store<ROWS_OUT, W, NT, LD>(out + q.b * a.out_sb + q.a0, a.out_sl, q.ncols, smem, tid);
+      tile_store<ROWS_OUT, W, NT, LD>(static_cast<float2 *>(a.out[q.solve]) + q.b * a.out_sb + q.a0,
+                                      a.out_sl, q.ncols, smem, tid);
     } else {
       if (c < q.ncols) {
-        float2 *line = out + (q.a0 + c) * a.out_st + q.b * a.out_sb;
+        float2 *line = static_cast<float2 *>(a.out[q.solve]) + (q.a0 + c) * a.out_st + q.b * a.out_sb;
 #pragma unroll
         for (int i = 0; i < E; ++i)
           if (!CROP || i < E / 2) line[t + T * i] = v[i];
@@ -200,8 +206,6 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
   const int g = lane / T, t = lane % T;
   const int c = wave * LPW + g;  // complex line: real lines 2c, 2c + 1
   float2 *xch = smem + c * C::SLOTS;
-  const float *__restrict__ in = static_cast<const float *>(a.in);
-  float2 *__restrict__ out = static_cast<float2 *>(a.out);
 
   Twiddles<L> tw;
   tw.load(a.tw, t);
@@ -210,6 +214,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
   float2 vn[E];
   auto fetch = [&](int tile) {
     const TileCoord q = tile_coord(a, tile, W);
+    const float *__restrict__ in = static_cast<const float *>(a.in[q.solve]);
     if constexpr (IN_TILED) {
       pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
     } else {
@@ -274,7 +279,8 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
       }
     }
     __syncthreads();
-    tile_store<ROWS_OUT, W, NT, LDC>(out + q.b * a.out_sb + q.a0, a.out_sl, q.ncols, smem, tid);
+    tile_store<ROWS_OUT, W, NT, LDC>(static_cast<float2 *>(a.out[q.solve]) + q.b * a.out_sb + q.a0,
+                                     a.out_sl, q.ncols, smem, tid);
     tile = next;
   }
 }
@@ -294,8 +300,6 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
   const int g = lane / T, t = lane % T;
   const int c = wave * LPW + g;
   float2 *xch = smem + c * C::SLOTS;
-  const float2 *__restrict__ in = static_cast<const float2 *>(a.in);
-  float *__restrict__ out = static_cast<float *>(a.out);
 
   Twiddles<L> tw;
   tw.load(a.tw, t);
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
   int tile = blockIdx.x;
   if (tile < a.ntiles) {
     const TileCoord q = tile_coord(a, tile, W);
-    pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
+    pf.load(static_cast<const float2 *>(a.in[q.solve]) + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
   }
   while (tile < a.ntiles) {
     const TileCoord q = tile_coord(a, tile, W);
@@ -329,7 +333,8 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
     }
     if (next < a.ntiles) {
       const TileCoord qn = tile_coord(a, next, W);
-      pf.load(in + qn.b * a.in_sb + qn.a0, a.in_sl, qn.ncols, tid);
+      pf.load(static_cast<const float2 *>(a.in[qn.solve]) + qn.b * a.in_sb + qn.a0, a.in_sl, qn.ncols,
+              tid);
     }
     __syncthreads();
 
@@ -342,10 +347,11 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
         if (!CROP || i < E / 2)
           *reinterpret_cast<float2 *>(smem_f + (t + T * i) * LDR + 2 * c) = v[i];
       __syncthreads();
-      tile_store<ROWS_OUT, W, NT, LDR>(out + q.b * a.out_sb + q.a0, a.out_sl, q.ncols, smem_f, tid);
+      tile_store<ROWS_OUT, W, NT, LDR>(static_cast<float *>(a.out[q.solve]) + q.b * a.out_sb + q.a0,
+                                       a.out_sl, q.ncols, smem_f, tid);
     } else {
       const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
-      float *l0 = out + (q.a0 + 2 * c) * a.out_st + q.b * a.out_sb;
+      float *l0 = static_cast<float *>(a.out[q.solve]) + (q.a0 + 2 * c) * a.out_st + q.b * a.out_sb;
       float *l1 = l0 + a.out_st;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -361,14 +367,16 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
 
 // ------------------------------------------------------------------ P3
 struct ConvParams {
-  float2 *data;       // A2, lines along r contiguous
+  float2 *data;       // A2 of the first solve, lines along r contiguous
+  long long solve_stride;  // elements between the A2 arrays of consecutive solves
   const float *kf;    // [k_p][k_q'][k_r'] float32, 1/(S1 S2 S3) folded in
   const float2 *tw;
   int st_q, st_p;     // element strides of line (k_p, k_q)
   int S_q;
   int kq_half;        // S_q/2 + 1
   int H;              // number of k_p planes
-  int nrows;          // H * kq_half kernel rows
+  int nrows;          // H * kq_half kernel rows per solve
+  int nsolve;
 };
 
 constexpr int kConvWaves = 4;
@@ -387,27 +395,31 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   float2 *xch = smem + (wave * LPW + g) * SLOTS;
 
   const int row0 = (blockIdx.x * kConvWaves + wave) * LPW + g;
-  if (row0 >= a.nrows) return;  // no barriers below: groups run independently
+  if (row0 >= a.nrows * a.nsolve) return;  // no barriers below: groups run independently
 
   Twiddles<L> tw;
   tw.load(a.tw, t);
 
+  // rows are (solve, k_p, k_q') in mixed radix; walk them with carries
   const int stride = gridDim.x * kConvWaves * LPW;
-  const int dkp = stride / a.kq_half, dkq = stride % a.kq_half;
-  int kp = row0 / a.kq_half, kqf = row0 % a.kq_half, rep = 0;
+  const int dsolve = stride / a.nrows, dr = stride % a.nrows;
+  const int dkp = dr / a.kq_half, dkq = dr % a.kq_half;
+  int solve = row0 / a.nrows;
+  const int r0 = row0 % a.nrows;
+  int kp = r0 / a.kq_half, kqf = r0 % a.kq_half, rep = 0;
 
   struct Item {
     float2 v[E];
     float k[E];
-    int off;
+    float2 *line;
     bool live;
   };
   auto fetch = [&](Item &it) {
-    it.live = kp < a.H;
+    it.live = solve < a.nsolve;
     if (!it.live) return;
     const int kq = rep == 0 ? kqf : a.S_q - kqf;
-    it.off = kp * a.st_p + kq * a.st_q;
-    const float2 *line = a.data + it.off;
+    it.line = a.data + solve * a.solve_stride + (kp * a.st_p + kq * a.st_q);
+    const float2 *line = it.line;
     const float *krow = a.kf + (kp * a.kq_half + kqf) * KR;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -424,9 +436,14 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
       rep = 0;
       kqf += dkq;
       kp += dkp;
+      solve += dsolve;
       if (kqf >= a.kq_half) {
         kqf -= a.kq_half;
         ++kp;
+      }
+      if (kp >= a.H) {
+        kp -= a.H;
+        ++solve;
       }
     }
   };
@@ -435,10 +452,9 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
 #pragma unroll
     for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
     fft_line<L, true>(it.v, tw, xch, t);
-    float2 *line = a.data + it.off;
 #pragma unroll
     for (int i = 0; i < E; ++i)
-      if (!PC || i < E / 2) line[t + T * i] = it.v[i];
+      if (!PC || i < E / 2) it.line[t + T * i] = it.v[i];
   };
 
   Item A, B;
@@ -471,10 +487,12 @@ int device_cu_count() {
   return cus;
 }
 
-PassParams make_params(const Pass &P, const void *in, void *out, const float2 *tw, int W) {
+PassParams make_params(const Pass &P, const PassIO &io, const float2 *tw, int W) {
   PassParams a;
-  a.in = in;
-  a.out = out;
+  for (int j = 0; j < kMaxBatch; ++j) {
+    a.in[j] = j < io.count ? io.in[j] : nullptr;
+    a.out[j] = j < io.count ? io.out[j] : nullptr;
+  }
   a.tw = tw;
   a.in_sl = int(P.in_s[0]);
   a.in_st = int(P.in_s[1]);
@@ -484,7 +502,8 @@ PassParams make_params(const Pass &P, const void *in, void *out, const float2 *t
   a.out_sb = int(P.out_s[2]);
   a.ext_tile = P.ext_tile;
   a.tiles_per_batch = (P.ext_tile + W - 1) / W;
-  a.ntiles = a.tiles_per_batch * P.ext_batch;
+  a.tiles_per_solve = a.tiles_per_batch * P.ext_batch;
+  a.ntiles = a.tiles_per_solve * io.count;
   return a;
 }
 
@@ -500,9 +519,9 @@ int persistent_grid(K kernel, int threads, int ntiles) {
 }
 
 template <int L, bool INV, bool IT, bool OT, bool PC>
-hipError_t launch_c2c(const Pass &P, const void *in, void *out, const float2 *tw, hipStream_t s) {
+hipError_t launch_c2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
   using C = Geo<L>;
-  PassParams a = make_params(P, in, out, tw, C::G);
+  PassParams a = make_params(P, io, tw, C::G);
   auto k = c2c_kernel<L, INV, IT, OT, PC>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
@@ -511,9 +530,9 @@ hipError_t launch_c2c(const Pass &P, const void *in, void *out, const float2 *tw
 }
 
 template <int L, bool IT, bool PAD>
-hipError_t launch_r2c(const Pass &P, const void *in, void *out, const float2 *tw, hipStream_t s) {
+hipError_t launch_r2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
   using C = Geo<L>;
-  PassParams a = make_params(P, in, out, tw, 2 * C::G);
+  PassParams a = make_params(P, io, tw, 2 * C::G);
   auto k = r2c_kernel<L, IT, PAD>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
@@ -522,9 +541,9 @@ hipError_t launch_r2c(const Pass &P, const void *in, void *out, const float2 *tw
 }
 
 template <int L, bool OT, bool CROP>
-hipError_t launch_c2r(const Pass &P, const void *in, void *out, const float2 *tw, hipStream_t s) {
+hipError_t launch_c2r(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
   using C = Geo<L>;
-  PassParams a = make_params(P, in, out, tw, 2 * C::G);
+  PassParams a = make_params(P, io, tw, 2 * C::G);
   auto k = c2r_kernel<L, OT, CROP>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
@@ -533,10 +552,12 @@ hipError_t launch_c2r(const Pass &P, const void *in, void *out, const float2 *tw
 }
 
 template <int L, bool PC>
-hipError_t launch_conv(const Pass &P, void *data, const float2 *tw, const float *kf, int S_q,
-                       hipStream_t s) {
+hipError_t launch_conv(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                       int S_q, hipStream_t s) {
   ConvParams a;
-  a.data = static_cast<float2 *>(data);
+  a.data = static_cast<float2 *>(io.out[0]);
+  a.solve_stride = io.conv_stride;
+  a.nsolve = io.count;
   a.kf = kf;
   a.tw = tw;
   a.st_q = int(P.in_s[1]);
@@ -547,7 +568,7 @@ hipError_t launch_conv(const Pass &P, void *data, const float2 *tw, const float 
   a.nrows = P.ext_batch * a.kq_half;
   constexpr int LPW = 64 / (L / Shape<L>::E);
   const long long groups_per_block = (long long)kConvWaves * LPW;
-  const long long need = (a.nrows + groups_per_block - 1) / groups_per_block;
+  const long long need = ((long long)a.nrows * a.nsolve + groups_per_block - 1) / groups_per_block;
   auto k = conv_kernel<L, PC>;
   const int blocks = persistent_grid(k, kConvWaves * 64, int(need < (1 << 30) ? need : (1 << 30)));
   if (blocks <= 0) return hipSuccess;
@@ -558,47 +579,48 @@ hipError_t launch_conv(const Pass &P, void *data, const float2 *tw, const float 
 }  // namespace
 
 template <int L>
-hipError_t launch_for_length(const Pass &P, const void *in, void *out, const float2 *tw,
-                             const float *kf, int S_q, hipStream_t s) {
+hipError_t launch_for_length(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                             int S_q, hipStream_t s) {
   const bool it = P.in_tiled, ot = P.out_tiled;
   switch (P.kind) {
     case KIND_R2C:
-      if (it) return P.pad ? launch_r2c<L, true, true>(P, in, out, tw, s)
-                           : launch_r2c<L, true, false>(P, in, out, tw, s);
-      return P.pad ? launch_r2c<L, false, true>(P, in, out, tw, s)
-                   : launch_r2c<L, false, false>(P, in, out, tw, s);
+      if (it) return P.pad ? launch_r2c<L, true, true>(P, io, tw, s)
+                           : launch_r2c<L, true, false>(P, io, tw, s);
+      return P.pad ? launch_r2c<L, false, true>(P, io, tw, s)
+                   : launch_r2c<L, false, false>(P, io, tw, s);
     case KIND_FWD:
-      if (it) return P.pad ? launch_c2c<L, false, true, true, true>(P, in, out, tw, s)
-                           : launch_c2c<L, false, true, true, false>(P, in, out, tw, s);
-      return P.pad ? launch_c2c<L, false, false, true, true>(P, in, out, tw, s)
-                   : launch_c2c<L, false, false, true, false>(P, in, out, tw, s);
+      if (it) return P.pad ? launch_c2c<L, false, true, true, true>(P, io, tw, s)
+                           : launch_c2c<L, false, true, true, false>(P, io, tw, s);
+      return P.pad ? launch_c2c<L, false, false, true, true>(P, io, tw, s)
+                   : launch_c2c<L, false, false, true, false>(P, io, tw, s);
     case KIND_CONV:
-      return P.pad ? launch_conv<L, true>(P, out, tw, kf, S_q, s)
-                   : launch_conv<L, false>(P, out, tw, kf, S_q, s);
+      return P.pad ? launch_conv<L, true>(P, io, tw, kf, S_q, s)
+                   : launch_conv<L, false>(P, io, tw, kf, S_q, s);
     case KIND_INV:
-      if (ot) return P.crop ? launch_c2c<L, true, true, true, true>(P, in, out, tw, s)
-                            : launch_c2c<L, true, true, true, false>(P, in, out, tw, s);
-      return P.crop ? launch_c2c<L, true, true, false, true>(P, in, out, tw, s)
-                    : launch_c2c<L, true, true, false, false>(P, in, out, tw, s);
+      if (ot) return P.crop ? launch_c2c<L, true, true, true, true>(P, io, tw, s)
+                            : launch_c2c<L, true, true, true, false>(P, io, tw, s);
+      return P.crop ? launch_c2c<L, true, true, false, true>(P, io, tw, s)
+                    : launch_c2c<L, true, true, false, false>(P, io, tw, s);
     case KIND_C2R:
-      if (ot) return P.crop ? launch_c2r<L, true, true>(P, in, out, tw, s)
-                            : launch_c2r<L, true, false>(P, in, out, tw, s);
-      return P.crop ? launch_c2r<L, false, true>(P, in, out, tw, s)
-                    : launch_c2r<L, false, false>(P, in, out, tw, s);
+      if (ot) return P.crop ? launch_c2r<L, true, true>(P, io, tw, s)
+                            : launch_c2r<L, true, false>(P, io, tw, s);
+      return P.crop ? launch_c2r<L, false, true>(P, io, tw, s)
+                    : launch_c2r<L, false, false>(P, io, tw, s);
   }
   return hipErrorInvalidValue;
 }
 
 #if defined(PSN_ONLY_LENGTH)
-template hipError_t launch_for_length<PSN_ONLY_LENGTH>(const Pass &, const void *, void *,
+template hipError_t launch_for_length<PSN_ONLY_LENGTH>(const Pass &, const PassIO &,
                                                        const float2 *, const float *, int,
                                                        hipStream_t);
 #endif
 
 #else  // PSN_DISPATCH_ONLY
 
-hipError_t launch_pass(const Pass &P, const void *in, void *out, const float2 *tw,
-                       const float *kf, int S_q, hipStream_t s) {
+hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                       int S_q, hipStream_t s) {
+  if (io.count < 1 || io.count > kMaxBatch) return hipErrorInvalidValue;
   // shapes the layouts promise (checked here so no kernel ever runs on a
   // layout it was not written for)
   if (P.kind == KIND_R2C && !P.out_tiled) return hipErrorInvalidValue;
@@ -608,7 +630,7 @@ hipError_t launch_pass(const Pass &P, const void *in, void *out, const float2 *t
   if (P.kind == KIND_CONV && (P.in_tiled || P.out_tiled)) return hipErrorInvalidValue;
   switch (P.L) {
 #define PSN_CASE(LL) \
-  case LL: return launch_for_length<LL>(P, in, out, tw, kf, S_q, s);
+  case LL: return launch_for_length<LL>(P, io, tw, kf, S_q, s);
     PSN_CASE(4) PSN_CASE(6) PSN_CASE(8) PSN_CASE(12) PSN_CASE(16) PSN_CASE(24) PSN_CASE(32)
     PSN_CASE(48) PSN_CASE(64) PSN_CASE(96) PSN_CASE(128) PSN_CASE(192) PSN_CASE(256)
     PSN_CASE(384) PSN_CASE(512) PSN_CASE(768) PSN_CASE(1024)

@@ -206,3 +206,74 @@ def test_full_mixed_bc_large(torch_dev, name):
     rho32 = rho.astype(np.float32)
     V, _ = _gpu_solve(torch_dev, n, bc, rho32)
     _check(V, oracle.solve(rho32.astype(np.float64), bc, H), name)
+
+
+# ---------------------------------------------------------------- batches
+def _batch_cases():
+    from densities import BATCH_BCS, BATCH_EDGES
+    cases = []
+    i = 0
+    for e in BATCH_EDGES[:3]:
+        for bc in BATCH_BCS:
+            for _ in range(3 if e == 32 else 1):
+                cases.append(((e, e, e), bc, 900 + i))
+                i += 1
+    return cases
+
+
+def test_batch_chunks_equal_single_solves(torch_dev, monkeypatch):
+    """Chunked grouped launches (forced to 2 solves per launch) reproduce
+    the single-solve results bit for bit."""
+    torch = torch_dev
+    from densities import batch_density
+    monkeypatch.setenv("POISSON_BATCH_CHUNK_MB", "0.5")
+    cases = _batch_cases()
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    Vs = [torch.full_like(r, float("nan")) for r in rhos]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases))
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for i, (n, bc, _) in enumerate(cases):
+        single = P.Plan(n, bc, H).solve(rhos[i])
+        torch.cuda.synchronize()
+        assert torch.equal(single, Vs[i]), (i, n, bc)
+    # and one entry of each class against the oracle
+    seen = set()
+    for i, (n, bc, _) in enumerate(cases):
+        if bc in seen:
+            continue
+        seen.add(bc)
+        _check(Vs[i].cpu().numpy(), oracle.solve(rhos[i].cpu().numpy().astype(np.float64), bc, H),
+               f"batch {n} bc={bc}")
+
+
+def test_batch_graph_replay(torch_dev):
+    """A captured batch replays to the eager result, replay after replay,
+    with eager work and synchronization in between."""
+    torch = torch_dev
+    from densities import batch_density
+    cases = _batch_cases()
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases))
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    eager = [v.clone() for v in Vs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in Vs:
+            v.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert torch.equal(Vs[i], eager[i]), (rep, i)
+        # eager work between replays
+        B.solve(rhos, Vs)
+        torch.cuda.synchronize()
