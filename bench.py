@@ -94,7 +94,7 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def bench_batch(torch, P, dev, reps=5):
+def bench_batch(torch, P, dev, reps=5, precision=0):
     """512 mixed solves: a per-solve loop of poisson_solve, the grouped batch
     (poisson_batch_solve) and the same batch replayed from a HIP graph."""
     from densities import batch_density, batch_workload
@@ -107,8 +107,9 @@ def bench_batch(torch, P, dev, reps=5):
     plans = {}
     for n, bc, _ in items:
         if (n, bc) not in plans:
-            plans[(n, bc)] = P.Plan(n, bc, H)
-    B = P.Batch([it[0] for it in items], [it[1] for it in items], [H] * len(items))
+            plans[(n, bc)] = P.Plan(n, bc, H, precision=precision)
+    B = P.Batch([it[0] for it in items], [it[1] for it in items], [H] * len(items),
+                precision=precision)
     torch.cuda.synchronize()
 
     def loop():
@@ -143,9 +144,8 @@ def bench_batch(torch, P, dev, reps=5):
     torch.cuda.synchronize()
     t_graph = timed(g.replay)
     same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
-    out = {"workload": "batch512 (edges 32..128, 4 BC classes, 4 Gaussians)", "solves": len(items),
-           "alg_bytes": alg, "identical_results": bool(same)}
-    for name, t in (("fp32_loop", t_loop), ("fp32_batched", t_batch), ("fp32_batched_graph", t_graph)):
+    out = {"solves": len(items), "alg_bytes": alg, "identical_results": bool(same)}
+    for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph)):
         out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),
                      "alg_gbs": alg / (t * 1e-3) / 1e9}
     return out
@@ -159,6 +159,7 @@ def main():
     ap.add_argument("--workload", default="free256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-solve batch")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision modes")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy (counter calibration)")
     args = ap.parse_args()
@@ -246,13 +247,39 @@ def main():
         "passes_ms": dict(zip(PASS_NAMES, per_pass)),
         "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
     }
+    # split-precision modes on the same workload: time and accuracy
+    if not args.no_split:
+        out["split"] = {}
+        for prec, name in ((P.POISSON_SPLIT_FP16, "fp16x2"), (P.POISSON_SPLIT_BF16, "bf16x3")):
+            sp = P.Plan(n, bc, H, precision=prec)
+            Vs = torch.empty_like(r)
+            for _ in range(3):
+                sp.solve(r, Vs, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                P.poisson_solve(sp.handle, r, Vs, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / args.steps
+            out["split"][name] = {"ms_per_solve": t, "solves_per_s": 1000.0 / t,
+                                  "V": Vs.cpu().numpy()}
+            sp.close()
     if not args.no_batch:
-        out["batch"] = bench_batch(torch, P, dev)
+        out["batch"] = {"workload": "batch512 (edges 32..128, 4 BC classes, 4 Gaussians)",
+                        "fp32": bench_batch(torch, P, dev),
+                        "split_fp16x2": bench_batch(torch, P, dev, precision=P.POISSON_SPLIT_FP16)}
     if not args.no_cpu_baseline:
         V_ref, cb = cpu_baseline(rho32, n, bc)
         out["cpu_baseline"] = cb
         diff = V_gpu.astype(np.float64) - V_ref
         out["rel_l2_vs_oracle"] = float(np.linalg.norm(diff) / np.linalg.norm(V_ref))
+        for name, rec in out.get("split", {}).items():
+            d = rec["V"].astype(np.float64) - V_ref
+            rec["rel_l2_vs_oracle"] = float(np.linalg.norm(d) / np.linalg.norm(V_ref))
+    for rec in out.get("split", {}).values():
+        rec.pop("V", None)
     print(json.dumps(out), flush=True)
 
 

@@ -54,8 +54,9 @@ def build(jobs=None, verbose=False):
         tasks.append((os.path.join(CSRC, s), os.path.join(BUILD, s.rsplit(".", 1)[0] + ".o"), ()))
     # one object per length group, each instantiating the launchers for its lengths
     for L in PASS_LENGTHS:
-        tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, f"passes_{L}.o"),
-                      (f"-DPSN_ONLY_LENGTH={L}",)))
+        for mode in (0, 1, 2):  # float32, split fp16, split bf16
+            tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, f"passes_{L}_{mode}.o"),
+                          (f"-DPSN_ONLY_LENGTH={L}", f"-DPSN_ONLY_MODE={mode}")))
     tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, "passes_dispatch.o"),
                   ("-DPSN_DISPATCH_ONLY=1",)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:

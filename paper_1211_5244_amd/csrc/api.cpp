@@ -86,9 +86,9 @@ struct poisson_batch_s {
 namespace {
 
 int check_precision(int precision) {
-  if (precision == POISSON_FP32) return POISSON_OK;
-  if (precision == POISSON_SPLIT_FP16 || precision == POISSON_SPLIT_BF16)
-    return fail(POISSON_E_UNSUPPORTED, "split-precision modes are not available in this build");
+  if (precision == POISSON_FP32 || precision == POISSON_SPLIT_FP16 ||
+      precision == POISSON_SPLIT_BF16)
+    return POISSON_OK;
   return fail(POISSON_E_ARG, "precision must be POISSON_FP32, POISSON_SPLIT_FP16 or POISSON_SPLIT_BF16");
 }
 
@@ -352,7 +352,7 @@ int enqueue_passes(poisson_plan_t P, int count, const float *const *rho, float *
         default: io.in[j] = A1; io.out[j] = V[j]; break;
       }
     }
-    hipError_t e = psn::launch_pass(g.pass[k], io, tws[k], P->kf32, g.S[q], s);
+    hipError_t e = psn::launch_pass(g.pass[k], io, tws[k], P->kf32, g.S[q], P->precision, s);
     if (e != hipSuccess) return hip_fail(e, "pass launch");
   }
   return POISSON_OK;

@@ -23,9 +23,11 @@ struct PassIO {
 // One pass on `stream` for io.count solves: reads io.in[j], writes io.out[j]
 // (complex intermediates are float2, density and potential float).  `tw` is
 // the table exp(-2 pi i n / L), n = 0..L-1, of the pass's length; `kf` the
-// float32 K^F in pass order (conv pass only).  Returns a hipError_t.
+// float32 K^F in pass order (conv pass only).  `mode` selects float32
+// radix stages (0) or split-precision matrix-core radix-8 stages (1: fp16
+// hi+lo, 2: bf16 three-way).  Returns a hipError_t.
 hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
-                       int S_q, hipStream_t stream);
+                       int S_q, int mode, hipStream_t stream);
 
 // float64 K^F octant of the default Green's function (layout of the C ABI:
 // k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.

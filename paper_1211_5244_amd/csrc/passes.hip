@@ -30,13 +30,14 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_core.h"
+#include "fft_split.h"
 #include "kernels.h"
 
 namespace psn {
 
-template <int L>
-hipError_t launch_for_length(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
-                             int S_q, hipStream_t s);
+template <int L, int MODE>
+hipError_t launch_for_mode(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                           int S_q, hipStream_t s);
 
 #if !defined(PSN_DISPATCH_ONLY)
 
@@ -66,6 +67,33 @@ template <int L> struct Geo {
 };
 
 template <int A, int B> constexpr int cmax() { return A > B ? A : B; }
+
+// The line transform of a kernel: float32 radix stages on the vector ALUs
+// (MODE_FP32), or radix-8 stages as split-precision DFT matmuls on the
+// matrix cores (MODE_SPLIT_*).  `line` is this line group's LDS region,
+// `wave_lines` the first region of its wavefront.
+template <int L, int MODE> struct LineEngine {
+  SplitTwiddles<L> tw;
+  SplitOps<MODE> ops;
+  __device__ __forceinline__ void init(const float2 *tab, int lane) {
+    tw.load(tab, lane);
+    ops.init(lane);
+  }
+  template <bool INV>
+  __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
+                                      int lane) {
+    fft_line_split<L, INV, MODE>(v, tw, ops, wave_lines, lane);
+  }
+};
+template <int L> struct LineEngine<L, MODE_FP32> {
+  Twiddles<L> tw;
+  __device__ __forceinline__ void init(const float2 *tab, int lane) { tw.load(tab, lane % kT<L>); }
+  template <bool INV>
+  __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
+                                      int lane) {
+    fft_line<L, INV>(v, tw, line, lane % kT<L>);
+  }
+};
 
 // A ROWS x W tile moved between HBM (rows at stride `sl`, W consecutive
 // elements per row) and LDS (row stride LD) by all NT threads, through
@@ -115,7 +143,7 @@ __device__ __forceinline__ TileCoord tile_coord(const PassParams &a, int tile, i
 }
 
 // ------------------------------------------------------------- P2 / P4
-template <int L, bool INV, bool IN_TILED, bool OUT_TILED, bool PC>
+template <int L, bool INV, bool IN_TILED, bool OUT_TILED, bool PC, int MODE>
 __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
   using C = Geo<L>;
   constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = C::G, LD = W + 1;
@@ -129,8 +157,9 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
   const int c = wave * LPW + g;
   float2 *xch = smem + c * C::SLOTS;
 
-  Twiddles<L> tw;
-  tw.load(a.tw, t);
+  float2 *wave_lines = smem + wave * LPW * C::SLOTS;
+  LineEngine<L, MODE> eng;
+  eng.init(a.tw, lane);
 
   TileRegs<ROWS_IN, W, NT, LD, float2> pf;
   float2 vn[E];
@@ -158,9 +187,10 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
     if constexpr (IN_TILED) {
       pf.to_lds(smem, tid);
       __syncthreads();
+      const bool ok = c < q.ncols;  // columns past a ragged edge hold stale LDS
 #pragma unroll
       for (int i = 0; i < E; ++i)
-        v[i] = (!PAD || i < E / 2) ? smem[(t + T * i) * LD + c] : make_float2(0.f, 0.f);
+        v[i] = ((!PAD || i < E / 2) && ok) ? smem[(t + T * i) * LD + c] : make_float2(0.f, 0.f);
       if (next < a.ntiles) fetch(next);
       __syncthreads();  // the tile region becomes exchange space
     } else {
@@ -169,7 +199,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    fft_line<L, INV>(v, tw, xch, t);
+    eng.template run<INV>(v, xch, wave_lines, lane);
 
     if constexpr (OUT_TILED) {
       __syncthreads();  // every line is done exchanging
@@ -192,7 +222,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
 }
 
 // ------------------------------------------------------------------ P1
-template <int L, bool IN_TILED, bool PAD>
+template <int L, bool IN_TILED, bool PAD, int MODE>
 __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
   using C = Geo<L>;
   constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = 2 * C::G;
@@ -207,8 +237,9 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
   const int c = wave * LPW + g;  // complex line: real lines 2c, 2c + 1
   float2 *xch = smem + c * C::SLOTS;
 
-  Twiddles<L> tw;
-  tw.load(a.tw, t);
+  float2 *wave_lines = smem + wave * LPW * C::SLOTS;
+  LineEngine<L, MODE> eng;
+  eng.init(a.tw, lane);
 
   TileRegs<ROWS_IN, W, NT, LDR, float> pf;
   float2 vn[E];
@@ -240,11 +271,14 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
     if constexpr (IN_TILED) {
       pf.to_lds(smem_f, tid);
       __syncthreads();
+      const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
 #pragma unroll
-      for (int i = 0; i < E; ++i)
-        v[i] = (!PAD || i < E / 2)
-                   ? *reinterpret_cast<const float2 *>(smem_f + (t + T * i) * LDR + 2 * c)
-                   : make_float2(0.f, 0.f);
+      for (int i = 0; i < E; ++i) {
+        const float2 x = (!PAD || i < E / 2)
+                             ? *reinterpret_cast<const float2 *>(smem_f + (t + T * i) * LDR + 2 * c)
+                             : make_float2(0.f, 0.f);
+        v[i] = make_float2(ok0 ? x.x : 0.f, ok1 ? x.y : 0.f);
+      }
       if (next < a.ntiles) fetch(next);
       __syncthreads();
     } else {
@@ -253,7 +287,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    fft_line<L, false>(v, tw, xch, t);
+    eng.template run<false>(v, xch, wave_lines, lane);
 
     // separate the two real lines: needs Z[L - k] from the mirrored lane
 #pragma unroll
@@ -286,7 +320,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
 }
 
 // ------------------------------------------------------------------ P5
-template <int L, bool OUT_TILED, bool CROP>
+template <int L, bool OUT_TILED, bool CROP, int MODE>
 __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
   using C = Geo<L>;
   constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = 2 * C::G;
@@ -301,8 +335,9 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
   const int c = wave * LPW + g;
   float2 *xch = smem + c * C::SLOTS;
 
-  Twiddles<L> tw;
-  tw.load(a.tw, t);
+  float2 *wave_lines = smem + wave * LPW * C::SLOTS;
+  LineEngine<L, MODE> eng;
+  eng.init(a.tw, lane);
 
   TileRegs<ROWS_IN, W, NT, LDC, float2> pf;
   int tile = blockIdx.x;
@@ -317,12 +352,14 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
     __syncthreads();
     pf.to_lds(smem, tid);
     __syncthreads();
+    const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int k = t + T * i;
       const bool direct = i < E / 2 || k == L / 2;
       const int kk = direct ? k : L - k;
-      float2 x0 = smem[kk * LDC + 2 * c], x1 = smem[kk * LDC + 2 * c + 1];
+      float2 x0 = ok0 ? smem[kk * LDC + 2 * c] : make_float2(0.f, 0.f);
+      float2 x1 = ok1 ? smem[kk * LDC + 2 * c + 1] : make_float2(0.f, 0.f);
       if (kk == 0 || kk == L / 2) {
         // DC and Nyquist coefficients of a real line are real
         x0.y = 0.f;
@@ -338,7 +375,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
     }
     __syncthreads();
 
-    fft_line<L, true>(v, tw, xch, t);
+    eng.template run<true>(v, xch, wave_lines, lane);
 
     if constexpr (OUT_TILED) {
       __syncthreads();
@@ -385,7 +422,9 @@ constexpr int kConvWaves = 4;
 // (K^F is even in k_q); the mirror line re-reads the row from cache.  Each
 // line group walks its rows in order with two line buffers: the next line
 // (and its kernel values) is loaded while the current one is transformed.
-template <int L, bool PC>
+// The walk is wavefront-uniform (a group without work transforms zeros and
+// stores nothing) so matrix-core stages always run on whole wavefronts.
+template <int L, bool PC, int MODE>
 __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T, KR = L / 2 + 1;
   constexpr int SLOTS = line_lds_slots<L>();
@@ -393,12 +432,13 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane / T, t = lane % T;
   float2 *xch = smem + (wave * LPW + g) * SLOTS;
+  float2 *wave_lines = smem + wave * LPW * SLOTS;
 
   const int row0 = (blockIdx.x * kConvWaves + wave) * LPW + g;
-  if (row0 >= a.nrows * a.nsolve) return;  // no barriers below: groups run independently
+  if (!__any(row0 < a.nrows * a.nsolve)) return;  // whole wavefront idle
 
-  Twiddles<L> tw;
-  tw.load(a.tw, t);
+  LineEngine<L, MODE> eng;
+  eng.init(a.tw, lane);
 
   // rows are (solve, k_p, k_q') in mixed radix; walk them with carries
   const int stride = gridDim.x * kConvWaves * LPW;
@@ -416,16 +456,15 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   };
   auto fetch = [&](Item &it) {
     it.live = solve < a.nsolve;
-    if (!it.live) return;
     const int kq = rep == 0 ? kqf : a.S_q - kqf;
-    it.line = a.data + solve * a.solve_stride + (kp * a.st_p + kq * a.st_q);
+    it.line = a.data + (it.live ? solve * a.solve_stride + (kp * a.st_p + kq * a.st_q) : 0);
     const float2 *line = it.line;
-    const float *krow = a.kf + (kp * a.kq_half + kqf) * KR;
+    const float *krow = a.kf + (it.live ? (kp * a.kq_half + kqf) * KR : 0);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int k = t + T * i;
-      it.v[i] = (!PC || i < E / 2) ? line[k] : make_float2(0.f, 0.f);
-      it.k[i] = krow[k <= L / 2 ? k : L - k];
+      it.v[i] = ((!PC || i < E / 2) && it.live) ? line[k] : make_float2(0.f, 0.f);
+      it.k[i] = it.live ? krow[k <= L / 2 ? k : L - k] : 0.f;
     }
   };
   auto advance = [&]() {
@@ -448,13 +487,15 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     }
   };
   auto process = [&](Item &it) {
-    fft_line<L, false>(it.v, tw, xch, t);
+    eng.template run<false>(it.v, xch, wave_lines, lane);
 #pragma unroll
     for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
-    fft_line<L, true>(it.v, tw, xch, t);
+    eng.template run<true>(it.v, xch, wave_lines, lane);
+    if (it.live) {
 #pragma unroll
-    for (int i = 0; i < E; ++i)
-      if (!PC || i < E / 2) it.line[t + T * i] = it.v[i];
+      for (int i = 0; i < E; ++i)
+        if (!PC || i < E / 2) it.line[t + T * i] = it.v[i];
+    }
   };
 
   Item A, B;
@@ -464,11 +505,11 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     fetch(B);
     advance();
     process(A);
-    if (!B.live) break;
+    if (!__any(B.live)) break;
     fetch(A);
     advance();
     process(B);
-    if (!A.live) break;
+    if (!__any(A.live)) break;
   }
 }
 
@@ -518,40 +559,40 @@ int persistent_grid(K kernel, int threads, int ntiles) {
   return int(ntiles < cap ? ntiles : cap);
 }
 
-template <int L, bool INV, bool IT, bool OT, bool PC>
+template <int L, int MODE, bool INV, bool IT, bool OT, bool PC>
 hipError_t launch_c2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
   using C = Geo<L>;
   PassParams a = make_params(P, io, tw, C::G);
-  auto k = c2c_kernel<L, INV, IT, OT, PC>;
+  auto k = c2c_kernel<L, INV, IT, OT, PC, MODE>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
-template <int L, bool IT, bool PAD>
+template <int L, int MODE, bool IT, bool PAD>
 hipError_t launch_r2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
   using C = Geo<L>;
   PassParams a = make_params(P, io, tw, 2 * C::G);
-  auto k = r2c_kernel<L, IT, PAD>;
+  auto k = r2c_kernel<L, IT, PAD, MODE>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
-template <int L, bool OT, bool CROP>
+template <int L, int MODE, bool OT, bool CROP>
 hipError_t launch_c2r(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
   using C = Geo<L>;
   PassParams a = make_params(P, io, tw, 2 * C::G);
-  auto k = c2r_kernel<L, OT, CROP>;
+  auto k = c2r_kernel<L, OT, CROP, MODE>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
-template <int L, bool PC>
+template <int L, int MODE, bool PC>
 hipError_t launch_conv(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
                        int S_q, hipStream_t s) {
   ConvParams a;
@@ -569,7 +610,7 @@ hipError_t launch_conv(const Pass &P, const PassIO &io, const float2 *tw, const 
   constexpr int LPW = 64 / (L / Shape<L>::E);
   const long long groups_per_block = (long long)kConvWaves * LPW;
   const long long need = ((long long)a.nrows * a.nsolve + groups_per_block - 1) / groups_per_block;
-  auto k = conv_kernel<L, PC>;
+  auto k = conv_kernel<L, PC, MODE>;
   const int blocks = persistent_grid(k, kConvWaves * 64, int(need < (1 << 30) ? need : (1 << 30)));
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(kConvWaves * 64), 0, s, a);
@@ -578,49 +619,50 @@ hipError_t launch_conv(const Pass &P, const PassIO &io, const float2 *tw, const 
 
 }  // namespace
 
-template <int L>
-hipError_t launch_for_length(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
-                             int S_q, hipStream_t s) {
+template <int L, int MODE>
+hipError_t launch_for_mode(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
+                           int S_q, hipStream_t s) {
   const bool it = P.in_tiled, ot = P.out_tiled;
   switch (P.kind) {
     case KIND_R2C:
-      if (it) return P.pad ? launch_r2c<L, true, true>(P, io, tw, s)
-                           : launch_r2c<L, true, false>(P, io, tw, s);
-      return P.pad ? launch_r2c<L, false, true>(P, io, tw, s)
-                   : launch_r2c<L, false, false>(P, io, tw, s);
+      if (it) return P.pad ? launch_r2c<L, MODE, true, true>(P, io, tw, s)
+                           : launch_r2c<L, MODE, true, false>(P, io, tw, s);
+      return P.pad ? launch_r2c<L, MODE, false, true>(P, io, tw, s)
+                   : launch_r2c<L, MODE, false, false>(P, io, tw, s);
     case KIND_FWD:
-      if (it) return P.pad ? launch_c2c<L, false, true, true, true>(P, io, tw, s)
-                           : launch_c2c<L, false, true, true, false>(P, io, tw, s);
-      return P.pad ? launch_c2c<L, false, false, true, true>(P, io, tw, s)
-                   : launch_c2c<L, false, false, true, false>(P, io, tw, s);
+      if (it) return P.pad ? launch_c2c<L, MODE, false, true, true, true>(P, io, tw, s)
+                           : launch_c2c<L, MODE, false, true, true, false>(P, io, tw, s);
+      return P.pad ? launch_c2c<L, MODE, false, false, true, true>(P, io, tw, s)
+                   : launch_c2c<L, MODE, false, false, true, false>(P, io, tw, s);
     case KIND_CONV:
-      return P.pad ? launch_conv<L, true>(P, io, tw, kf, S_q, s)
-                   : launch_conv<L, false>(P, io, tw, kf, S_q, s);
+      return P.pad ? launch_conv<L, MODE, true>(P, io, tw, kf, S_q, s)
+                   : launch_conv<L, MODE, false>(P, io, tw, kf, S_q, s);
     case KIND_INV:
-      if (ot) return P.crop ? launch_c2c<L, true, true, true, true>(P, io, tw, s)
-                            : launch_c2c<L, true, true, true, false>(P, io, tw, s);
-      return P.crop ? launch_c2c<L, true, true, false, true>(P, io, tw, s)
-                    : launch_c2c<L, true, true, false, false>(P, io, tw, s);
+      if (ot) return P.crop ? launch_c2c<L, MODE, true, true, true, true>(P, io, tw, s)
+                            : launch_c2c<L, MODE, true, true, true, false>(P, io, tw, s);
+      return P.crop ? launch_c2c<L, MODE, true, true, false, true>(P, io, tw, s)
+                    : launch_c2c<L, MODE, true, true, false, false>(P, io, tw, s);
     case KIND_C2R:
-      if (ot) return P.crop ? launch_c2r<L, true, true>(P, io, tw, s)
-                            : launch_c2r<L, true, false>(P, io, tw, s);
-      return P.crop ? launch_c2r<L, false, true>(P, io, tw, s)
-                    : launch_c2r<L, false, false>(P, io, tw, s);
+      if (ot) return P.crop ? launch_c2r<L, MODE, true, true>(P, io, tw, s)
+                            : launch_c2r<L, MODE, true, false>(P, io, tw, s);
+      return P.crop ? launch_c2r<L, MODE, false, true>(P, io, tw, s)
+                    : launch_c2r<L, MODE, false, false>(P, io, tw, s);
   }
   return hipErrorInvalidValue;
 }
 
-#if defined(PSN_ONLY_LENGTH)
-template hipError_t launch_for_length<PSN_ONLY_LENGTH>(const Pass &, const PassIO &,
-                                                       const float2 *, const float *, int,
-                                                       hipStream_t);
+#if defined(PSN_ONLY_LENGTH) && defined(PSN_ONLY_MODE)
+template hipError_t launch_for_mode<PSN_ONLY_LENGTH, PSN_ONLY_MODE>(const Pass &, const PassIO &,
+                                                                    const float2 *, const float *,
+                                                                    int, hipStream_t);
 #endif
 
 #else  // PSN_DISPATCH_ONLY
 
 hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
-                       int S_q, hipStream_t s) {
+                       int S_q, int mode, hipStream_t s) {
   if (io.count < 1 || io.count > kMaxBatch) return hipErrorInvalidValue;
+  if (mode < MODE_FP32 || mode > MODE_SPLIT_BF16) return hipErrorInvalidValue;
   // shapes the layouts promise (checked here so no kernel ever runs on a
   // layout it was not written for)
   if (P.kind == KIND_R2C && !P.out_tiled) return hipErrorInvalidValue;
@@ -629,8 +671,11 @@ hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const 
   if (P.kind == KIND_C2R && !P.in_tiled) return hipErrorInvalidValue;
   if (P.kind == KIND_CONV && (P.in_tiled || P.out_tiled)) return hipErrorInvalidValue;
   switch (P.L) {
-#define PSN_CASE(LL) \
-  case LL: return launch_for_length<LL>(P, io, tw, kf, S_q, s);
+#define PSN_CASE(LL)                                                           \
+  case LL:                                                                     \
+    if (mode == MODE_SPLIT_FP16) return launch_for_mode<LL, MODE_SPLIT_FP16>(P, io, tw, kf, S_q, s); \
+    if (mode == MODE_SPLIT_BF16) return launch_for_mode<LL, MODE_SPLIT_BF16>(P, io, tw, kf, S_q, s); \
+    return launch_for_mode<LL, MODE_FP32>(P, io, tw, kf, S_q, s);
     PSN_CASE(4) PSN_CASE(6) PSN_CASE(8) PSN_CASE(12) PSN_CASE(16) PSN_CASE(24) PSN_CASE(32)
     PSN_CASE(48) PSN_CASE(64) PSN_CASE(96) PSN_CASE(128) PSN_CASE(192) PSN_CASE(256)
     PSN_CASE(384) PSN_CASE(512) PSN_CASE(768) PSN_CASE(1024)

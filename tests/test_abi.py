@@ -110,10 +110,9 @@ def test_describe_rejects_bad_arguments(args, code):
     assert P.poisson_last_error()
 
 
-def test_split_precision_is_reported_unsupported():
-    with pytest.raises(P.PoissonError) as e:
-        P.poisson_plan_describe(64, 64, 64, 7, P.POISSON_SPLIT_FP16)
-    assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
+def test_precision_modes():
+    for prec in (P.POISSON_FP32, P.POISSON_SPLIT_FP16, P.POISSON_SPLIT_BF16):
+        assert P.poisson_plan_describe(64, 64, 64, 7, prec)["alg_bytes"] > 0
     with pytest.raises(P.PoissonError) as e:
         P.poisson_plan_describe(64, 64, 64, 7, 9)
     assert e.value.code == P._lib.POISSON_E_ARG

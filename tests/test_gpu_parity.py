@@ -35,8 +35,8 @@ def _density(n, bc, seed, count=6):
     return rho.astype(np.float32)
 
 
-def _gpu_solve(torch, n, bc, rho32, plan=None):
-    plan = plan or P.Plan(n, bc, H)
+def _gpu_solve(torch, n, bc, rho32, plan=None, precision=P.POISSON_FP32):
+    plan = plan or P.Plan(n, bc, H, precision=precision)
     r = torch.from_numpy(rho32).cuda()
     V = plan.solve(r)
     torch.cuda.synchronize()
@@ -277,3 +277,59 @@ def test_batch_graph_replay(torch_dev):
         # eager work between replays
         B.solve(rhos, Vs)
         torch.cuda.synchronize()
+
+
+# ------------------------------------------------------- split precision
+SPLITS = [pytest.param(P.POISSON_SPLIT_FP16, id="fp16x2"), pytest.param(P.POISSON_SPLIT_BF16, id="bf16x3")]
+
+
+@pytest.mark.parametrize("prec", SPLITS)
+@pytest.mark.parametrize("bc", range(8))
+@pytest.mark.parametrize("n", SMALL_SHAPES)
+def test_split_parity_small(torch_dev, n, bc, prec):
+    """Radix-8 stages on the matrix cores with split operands keep the
+    float32 bar against the float64 definition."""
+    rho = _density(n, bc, seed=100 + bc)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho, precision=prec)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"split{prec} {n} bc={bc}")
+
+
+@pytest.mark.parametrize("prec", SPLITS)
+@pytest.mark.parametrize("name", ["free128", "wire128", "surface128", "periodic128"])
+def test_split_parity_128(torch_dev, name, prec):
+    n, bc, rho = workload_density(name)
+    rho = rho.astype(np.float32)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho, precision=prec)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"split{prec} {name}")
+
+
+@pytest.mark.parametrize("prec", SPLITS)
+def test_split_full_free256(torch_dev, prec):
+    n, bc, rho = workload_density("free256")
+    rho32 = rho.astype(np.float32)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho32, precision=prec)
+    _check(V, oracle.solve(rho32.astype(np.float64), bc, H), f"split{prec} free256")
+
+
+@pytest.mark.parametrize("name", ["wire192x192x384", "surface384x192x384"])
+def test_split_fp16_mixed_bc_large(torch_dev, name):
+    n, bc, rho = workload_density(name)
+    rho32 = rho.astype(np.float32)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho32, precision=P.POISSON_SPLIT_FP16)
+    _check(V, oracle.solve(rho32.astype(np.float64), bc, H), f"split fp16 {name}")
+
+
+def test_split_batch_equals_single_solves(torch_dev):
+    torch = torch_dev
+    from densities import batch_density
+    cases = _batch_cases()
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases),
+                precision=P.POISSON_SPLIT_FP16)
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for i, (n, bc, _) in enumerate(cases):
+        single = P.Plan(n, bc, H, precision=P.POISSON_SPLIT_FP16).solve(rhos[i])
+        torch.cuda.synchronize()
+        assert torch.equal(single, Vs[i]), (i, n, bc)
