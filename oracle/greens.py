@@ -50,8 +50,10 @@ the last, fastest array axis.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft
 from scipy import special
 
 EULER_GAMMA = 0.57721566490153286061
@@ -138,7 +140,7 @@ def kernel_fourier(n, bc_mask, h):
     free_axes = tuple(2 - j for j in range(3) if (bc_mask >> j) & 1)
     if not free_axes:
         return mixed
-    kf = np.fft.fftn(mixed, axes=free_axes)
+    kf = scipy.fft.fftn(mixed, axes=free_axes, workers=os.cpu_count() or 1)
     scale = max(1.0, float(np.abs(kf.real).max()))
     if float(np.abs(kf.imag).max()) > 1e-9 * scale:
         raise AssertionError("kernel is not even: K^F has an imaginary part")
