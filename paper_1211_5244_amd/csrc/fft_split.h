@@ -136,6 +136,20 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Twiddle product with one fixed rounding order (one product rounded, the
+// other fused).  In a matrix-core stage a line's butterflies land in a block
+// chosen by the line's place in the wavefront, and every block is separate
+// unrolled code; if the compiler picked the fused form per block, a line's
+// result would depend on that place (a batched solve and a lone one would
+// differ in the last bit).
+template <bool INV> __device__ __forceinline__ float2 cmul_tw_fixed(float2 a, float2 w) {
+#pragma clang fp contract(off)
+  if constexpr (!INV)
+    return make_float2(__builtin_fmaf(a.x, w.x, -(a.y * w.y)), __builtin_fmaf(a.x, w.y, a.y * w.x));
+  else
+    return make_float2(__builtin_fmaf(a.x, w.x, a.y * w.y), __builtin_fmaf(a.y, w.x, -(a.x * w.y)));
+}
+
 // Twiddles of the split transform, read from the table exp(-2 pi i n / L)
 // (cached) when a stage needs them: the matrix-core path is short of
 // registers, so they are not held across lines.
@@ -175,7 +189,7 @@ __device__ __forceinline__ void split_stage(float2 *__restrict__ wl, const Split
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         float2 a = src[lds_pad(jj[b] + (2 * gq + u) * NB)];
-        if constexpr (S > 0) a = cmul_tw<INV>(a, tw((jj[b] % NS) * (2 * gq + u) * STEP));
+        if constexpr (S > 0) a = cmul_tw_fixed<INV>(a, tw((jj[b] % NS) * (2 * gq + u) * STEP));
         x[b][2 * u] = a.x;
         x[b][2 * u + 1] = a.y;
         cmax[b] = fmaxf(cmax[b], fmaxf(fabsf(a.x), fabsf(a.y)));

@@ -460,11 +460,37 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     it.line = a.data + (it.live ? solve * a.solve_stride + (kp * a.st_p + kq * a.st_q) : 0);
     const float2 *line = it.line;
     const float *krow = a.kf + (it.live ? (kp * a.kq_half + kqf) * KR : 0);
+    if constexpr (LPW == 1) {
+      // one line per wavefront: liveness is uniform, a scalar branch is free
+      if (__builtin_amdgcn_readfirstlane(int(it.live))) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int k = t + T * i;
+          it.k[i] = krow[k <= L / 2 ? k : L - k];
+          it.v[i] = (!PC || i < E / 2) ? line[k] : make_float2(0.f, 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          it.k[i] = 0.f;
+          it.v[i] = make_float2(0.f, 0.f);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
+      // branch-free: a dead item reads the first line and row (valid) and
+      // keeps zeros
       const int k = t + T * i;
-      it.v[i] = ((!PC || i < E / 2) && it.live) ? line[k] : make_float2(0.f, 0.f);
-      it.k[i] = it.live ? krow[k <= L / 2 ? k : L - k] : 0.f;
+      const float kv = krow[k <= L / 2 ? k : L - k];
+      it.k[i] = it.live ? kv : 0.f;
+      if (!PC || i < E / 2) {
+        const float2 x = line[k];
+        it.v[i] = it.live ? x : make_float2(0.f, 0.f);
+      } else {
+        it.v[i] = make_float2(0.f, 0.f);
+      }
     }
   };
   auto advance = [&]() {
@@ -491,7 +517,7 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
 #pragma unroll
     for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
     eng.template run<true>(it.v, xch, wave_lines, lane);
-    if (it.live) {
+    if (LPW == 1 ? bool(__builtin_amdgcn_readfirstlane(int(it.live))) : it.live) {
 #pragma unroll
       for (int i = 0; i < E; ++i)
         if (!PC || i < E / 2) it.line[t + T * i] = it.v[i];

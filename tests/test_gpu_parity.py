@@ -328,8 +328,14 @@ def test_split_batch_equals_single_solves(torch_dev):
     B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases),
                 precision=P.POISSON_SPLIT_FP16)
     B.solve(rhos, Vs)
+    again = [torch.empty_like(r) for r in rhos]
+    B.solve(rhos, again)
     torch.cuda.synchronize()
     for i, (n, bc, _) in enumerate(cases):
+        # the same batch call twice: bit for bit
+        assert torch.equal(Vs[i], again[i]), (i, n, bc)
         single = P.Plan(n, bc, H, precision=P.POISSON_SPLIT_FP16).solve(rhos[i])
         torch.cuda.synchronize()
+        # a line's place in its wavefront differs between a batched and a
+        # lone solve; the result must not depend on it
         assert torch.equal(single, Vs[i]), (i, n, bc)
