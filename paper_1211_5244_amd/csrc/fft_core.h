@@ -11,9 +11,10 @@
 // so no workgroup barrier is needed between stages.
 //
 // Zero padding (Section 3: the second half of a free axis is zero before its
-// transform) is known at compile time: elements i >= E/2 are literal zeros,
-// so the first stage's arithmetic on them folds away.  Likewise, outputs a
-// caller never stores (the crop after an inverse transform) are dead code.
+// transform) is known at compile time: elements i >= E/2 are never loaded,
+// and the first stage uses butterflies without their zero legs (ZHI).
+// Likewise, outputs a caller never stores (the crop after an inverse
+// transform) are dead code.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,10 +86,18 @@ template <bool INV> __device__ __forceinline__ float2 mul_mi(float2 a) {
 
 // ------------------------------------------------------------ small DFTs
 // Forward kernels use exp(-2 pi i jk / R), inverse exp(+2 pi i jk / R).
-template <bool INV> __device__ __forceinline__ void dft2(float2 *a) {
-  float2 t = a[1];
-  a[1] = csub(a[0], t);
-  a[0] = cadd(a[0], t);
+// ZHI: the upper half of the inputs (a[R/2..R-1]) is known to be zero, as in
+// the first stage of a transform of a zero-padded line.  Adding a literal
+// zero does not fold away in IEEE arithmetic (-0 + 0 = +0), so the first
+// radix-2 split is written out as copies instead.
+template <bool INV, bool ZHI = false> __device__ __forceinline__ void dft2(float2 *a) {
+  if constexpr (ZHI) {
+    a[1] = a[0];
+  } else {
+    float2 t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
 }
 
 template <bool INV> __device__ __forceinline__ void dft3(float2 *a) {
@@ -103,22 +112,39 @@ template <bool INV> __device__ __forceinline__ void dft3(float2 *a) {
   else { a[1] = cadd(m, icd); a[2] = csub(m, icd); }
 }
 
-template <bool INV> __device__ __forceinline__ void dft4(float2 *a) {
-  float2 d0 = cadd(a[0], a[2]), d2 = csub(a[0], a[2]);
-  float2 d1 = cadd(a[1], a[3]), d3 = mul_mi<INV>(csub(a[1], a[3]));
+template <bool INV, bool ZHI = false> __device__ __forceinline__ void dft4(float2 *a) {
+  float2 d0, d1, d2, d3;
+  if constexpr (ZHI) {
+    d0 = d2 = a[0];
+    d1 = a[1];
+    d3 = mul_mi<INV>(a[1]);
+  } else {
+    d0 = cadd(a[0], a[2]);
+    d2 = csub(a[0], a[2]);
+    d1 = cadd(a[1], a[3]);
+    d3 = mul_mi<INV>(csub(a[1], a[3]));
+  }
   a[0] = cadd(d0, d1);
   a[2] = csub(d0, d1);
   a[1] = cadd(d2, d3);
   a[3] = csub(d2, d3);
 }
 
-template <bool INV> __device__ __forceinline__ void dft8(float2 *a) {
+template <bool INV, bool ZHI = false> __device__ __forceinline__ void dft8(float2 *a) {
   constexpr float r = 0.70710678118654752440f;
   // radix-2 split between a[m] and a[m+4]
-  float2 b0 = cadd(a[0], a[4]), b4 = csub(a[0], a[4]);
-  float2 b1 = cadd(a[1], a[5]), b5 = csub(a[1], a[5]);
-  float2 b2 = cadd(a[2], a[6]), b6 = csub(a[2], a[6]);
-  float2 b3 = cadd(a[3], a[7]), b7 = csub(a[3], a[7]);
+  float2 b0, b1, b2, b3, b4, b5, b6, b7;
+  if constexpr (ZHI) {
+    b0 = b4 = a[0];
+    b1 = b5 = a[1];
+    b2 = b6 = a[2];
+    b3 = b7 = a[3];
+  } else {
+    b0 = cadd(a[0], a[4]); b4 = csub(a[0], a[4]);
+    b1 = cadd(a[1], a[5]); b5 = csub(a[1], a[5]);
+    b2 = cadd(a[2], a[6]); b6 = csub(a[2], a[6]);
+    b3 = cadd(a[3], a[7]); b7 = csub(a[3], a[7]);
+  }
   // odd half times w8^m (forward w8 = (1-i)/sqrt2)
   if constexpr (!INV) {
     b5 = make_float2(r * (b5.x + b5.y), r * (b5.y - b5.x));
@@ -137,11 +163,13 @@ template <bool INV> __device__ __forceinline__ void dft8(float2 *a) {
   a[1] = o[0]; a[3] = o[1]; a[5] = o[2]; a[7] = o[3];
 }
 
-template <int R, bool INV> __device__ __forceinline__ void dft(float2 *a) {
-  if constexpr (R == 2) dft2<INV>(a);
+// ZHI is used by the even radices; an odd radix ignores it (its zero inputs
+// do not fall in one half of the butterfly).
+template <int R, bool INV, bool ZHI = false> __device__ __forceinline__ void dft(float2 *a) {
+  if constexpr (R == 2) dft2<INV, ZHI>(a);
   else if constexpr (R == 3) dft3<INV>(a);
-  else if constexpr (R == 4) dft4<INV>(a);
-  else if constexpr (R == 8) dft8<INV>(a);
+  else if constexpr (R == 4) dft4<INV, ZHI>(a);
+  else if constexpr (R == 8) dft8<INV, ZHI>(a);
   else static_assert(R == 2, "unsupported radix");
 }
 
@@ -179,7 +207,10 @@ template <int L> struct Twiddles {
 };
 
 // ----------------------------------------------------------- the line FFT
-template <int L, int S, bool INV>
+// ZHI: elements i >= E/2 of every lane are zero on entry (a zero-padded line).
+// In the first stage butterfly b reads v[b + m B], m = 0..R-1, with E = R B,
+// so its zero legs are exactly m >= R/2.
+template <int L, int S, bool INV, bool ZHI = false>
 __device__ __forceinline__ void fft_stage(float2 (&v)[Shape<L>::E], const Twiddles<L> &tw,
                                           float2 *__restrict__ lds, int t) {
   constexpr int E = Shape<L>::E, R = Shape<L>::R[S], B = E / R, NS = span<L>(S), T = kT<L>;
@@ -193,7 +224,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[Shape<L>::E], const Twiddl
 #pragma unroll
       for (int m = 1; m < R; ++m) a[m] = cmul_tw<INV>(a[m], tw.w[OFF + b * (R - 1) + (m - 1)]);
     }
-    dft<R, INV>(a);
+    dft<R, INV, ZHI && S == 0>(a);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[b + m * B] = a[m];
   }
@@ -218,10 +249,10 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[Shape<L>::E], const Twiddl
 // Full forward (INV = false) or unnormalized inverse transform of the line
 // held by lanes t = 0..T-1 of this line group; lds is the group's region of
 // line_lds_slots<L>() float2.
-template <int L, bool INV>
+template <int L, bool INV, bool ZHI = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[Shape<L>::E], const Twiddles<L> &tw,
                                          float2 *__restrict__ lds, int t) {
-  fft_stage<L, 0, INV>(v, tw, lds, t);
+  fft_stage<L, 0, INV, ZHI>(v, tw, lds, t);
 }
 
 }  // namespace psn

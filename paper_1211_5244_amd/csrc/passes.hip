@@ -79,7 +79,8 @@ template <int L, int MODE> struct LineEngine {
     tw.load(tab, lane);
     ops.init(lane);
   }
-  template <bool INV>
+  // ZHI (upper half of the inputs zero) is not used by the matrix-core stages
+  template <bool INV, bool ZHI = false>
   __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
                                       int lane) {
     fft_line_split<L, INV, MODE>(v, tw, ops, wave_lines, lane);
@@ -88,10 +89,10 @@ template <int L, int MODE> struct LineEngine {
 template <int L> struct LineEngine<L, MODE_FP32> {
   Twiddles<L> tw;
   __device__ __forceinline__ void init(const float2 *tab, int lane) { tw.load(tab, lane % kT<L>); }
-  template <bool INV>
+  template <bool INV, bool ZHI = false>
   __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
                                       int lane) {
-    fft_line<L, INV>(v, tw, line, lane % kT<L>);
+    fft_line<L, INV, ZHI>(v, tw, line, lane % kT<L>);
   }
 };
 
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    eng.template run<INV>(v, xch, wave_lines, lane);
+    eng.template run<INV, PAD>(v, xch, wave_lines, lane);
 
     if constexpr (OUT_TILED) {
       __syncthreads();  // every line is done exchanging
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    eng.template run<false>(v, xch, wave_lines, lane);
+    eng.template run<false, PAD>(v, xch, wave_lines, lane);
 
     // separate the two real lines: needs Z[L - k] from the mirrored lane
 #pragma unroll
@@ -422,14 +423,16 @@ constexpr int kConvWaves = 4;
 // (K^F is even in k_q); the mirror line re-reads the row from cache.  Each
 // line group walks its rows in order with two line buffers: the next line
 // (and its kernel values) is loaded while the current one is transformed.
-// The walk is wavefront-uniform (a group without work transforms zeros and
-// stores nothing) so matrix-core stages always run on whole wavefronts.
+// The walk is wavefront-uniform (a group without work transforms the first
+// line of the array and stores nothing) so matrix-core stages always run on
+// whole wavefronts.  With one line per wavefront the walk is scalar.
 template <int L, bool PC, int MODE>
 __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T, KR = L / 2 + 1;
   constexpr int SLOTS = line_lds_slots<L>();
   __shared__ float2 smem[kConvWaves * LPW * SLOTS];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane / T, t = lane % T;
   float2 *xch = smem + (wave * LPW + g) * SLOTS;
   float2 *wave_lines = smem + wave * LPW * SLOTS;
@@ -458,39 +461,16 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     it.live = solve < a.nsolve;
     const int kq = rep == 0 ? kqf : a.S_q - kqf;
     it.line = a.data + (it.live ? solve * a.solve_stride + (kp * a.st_p + kq * a.st_q) : 0);
-    const float2 *line = it.line;
     const float *krow = a.kf + (it.live ? (kp * a.kq_half + kqf) * KR : 0);
-    if constexpr (LPW == 1) {
-      // one line per wavefront: liveness is uniform, a scalar branch is free
-      if (__builtin_amdgcn_readfirstlane(int(it.live))) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-          const int k = t + T * i;
-          it.k[i] = krow[k <= L / 2 ? k : L - k];
-          it.v[i] = (!PC || i < E / 2) ? line[k] : make_float2(0.f, 0.f);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-          it.k[i] = 0.f;
-          it.v[i] = make_float2(0.f, 0.f);
-        }
-      }
-      return;
-    }
+    // K^F is even along r: element k >= L/2 takes row entry L - k (i >= E/2
+    // holds exactly those k, and k = L/2 reads the same entry either way)
+    const float *kup = krow + t, *kdown = krow + (L - t);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      // branch-free: a dead item reads the first line and row (valid) and
-      // keeps zeros
       const int k = t + T * i;
-      const float kv = krow[k <= L / 2 ? k : L - k];
-      it.k[i] = it.live ? kv : 0.f;
-      if (!PC || i < E / 2) {
-        const float2 x = line[k];
-        it.v[i] = it.live ? x : make_float2(0.f, 0.f);
-      } else {
-        it.v[i] = make_float2(0.f, 0.f);
-      }
+      it.k[i] = i < E / 2 ? kup[T * i] : kdown[-T * i];
+      // the padding half: never read by the float32 first stage
+      it.v[i] = (!PC || i < E / 2) ? it.line[k] : make_float2(0.f, 0.f);
     }
   };
   auto advance = [&]() {
@@ -513,11 +493,11 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     }
   };
   auto process = [&](Item &it) {
-    eng.template run<false>(it.v, xch, wave_lines, lane);
+    eng.template run<false, PC>(it.v, xch, wave_lines, lane);
 #pragma unroll
     for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
     eng.template run<true>(it.v, xch, wave_lines, lane);
-    if (LPW == 1 ? bool(__builtin_amdgcn_readfirstlane(int(it.live))) : it.live) {
+    if (it.live) {
 #pragma unroll
       for (int i = 0; i < E; ++i)
         if (!PC || i < E / 2) it.line[t + T * i] = it.v[i];
