@@ -96,6 +96,23 @@ template <int L> struct LineEngine<L, MODE_FP32> {
   }
 };
 
+// Non-temporal hints, chosen by measurement on the 512-length passes (whole
+// solve, 2.62k -> 2.68k solves/s): every store of a pass output streams, and
+// so do the tiled loads (128-byte row segments of W lines); contiguous line
+// loads keep ordinary loads (streaming them cost 4-9%).  A streaming store
+// makes its own pass slower and the next one faster: the 256 MB last-level
+// cache then holds no dirty lines that the next pass would have to evict.
+typedef float psn_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(float2 *p, float2 v) {
+  __builtin_nontemporal_store(*reinterpret_cast<const psn_f2v *>(&v), reinterpret_cast<psn_f2v *>(p));
+}
+__device__ __forceinline__ void st_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ float2 ld_stream(const float2 *p) {
+  const psn_f2v v = __builtin_nontemporal_load(reinterpret_cast<const psn_f2v *>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+
 // A ROWS x W tile moved between HBM (rows at stride `sl`, W consecutive
 // elements per row) and LDS (row stride LD) by all NT threads, through
 // registers so the HBM side can be issued early.
@@ -108,7 +125,7 @@ template <int ROWS, int W, int NT, int LD, typename TE> struct TileRegs {
     for (int p = 0; p < PF; ++p) {
       const int idx = tid + p * NT;
       const int row = idx / W, col = idx % W;
-      if (idx < N && col < ncols) r[p] = base[row * sl + col];
+      if (idx < N && col < ncols) r[p] = ld_stream(&base[row * sl + col]);
     }
   }
   __device__ __forceinline__ void to_lds(TE *tile, int tid) const {
@@ -125,7 +142,7 @@ __device__ __forceinline__ void tile_store(TE *__restrict__ base, int sl, int nc
                                            const TE *tile, int tid) {
   for (int idx = tid; idx < ROWS * W; idx += NT) {
     const int row = idx / W, col = idx % W;
-    if (col < ncols) base[row * sl + col] = tile[row * LD + col];
+    if (col < ncols) st_stream(&base[row * sl + col], tile[row * LD + col]);
   }
 }
 
@@ -215,7 +232,7 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
         float2 *line = static_cast<float2 *>(a.out[q.solve]) + (q.a0 + c) * a.out_st + q.b * a.out_sb;
 #pragma unroll
         for (int i = 0; i < E; ++i)
-          if (!CROP || i < E / 2) line[t + T * i] = v[i];
+          if (!CROP || i < E / 2) st_stream(&line[t + T * i], v[i]);
       }
     }
     tile = next;
@@ -394,8 +411,8 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         if (!CROP || i < E / 2) {
-          if (ok0) l0[t + T * i] = v[i].x;
-          if (ok1) l1[t + T * i] = v[i].y;
+          if (ok0) st_stream(&l0[t + T * i], v[i].x);
+          if (ok1) st_stream(&l1[t + T * i], v[i].y);
         }
       }
     }
@@ -500,7 +517,7 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     if (it.live) {
 #pragma unroll
       for (int i = 0; i < E; ++i)
-        if (!PC || i < E / 2) it.line[t + T * i] = it.v[i];
+        if (!PC || i < E / 2) st_stream(&it.line[t + T * i], it.v[i]);
     }
   };
 
