@@ -144,8 +144,22 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     torch.cuda.synchronize()
     t_graph = timed(g.replay)
     same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
-    out = {"solves": len(items), "alg_bytes": alg, "identical_results": bool(same)}
-    for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph)):
+    # the autotuner: tile schedules per distinct plan, then the per-launch budget
+    chunk_mb = B.tune(rhos, Vs)
+    t_tuned = timed(batched)
+    same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
+    g2 = torch.cuda.CUDAGraph()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g2):
+            P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream(dev))
+    torch.cuda.synchronize()
+    t_tuned_graph = timed(g2.replay)
+    same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
+    out = {"solves": len(items), "alg_bytes": alg, "identical_results": bool(same),
+           "tuned_chunk_mb": chunk_mb}
+    for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph),
+                    ("batched_tuned", t_tuned), ("batched_tuned_graph", t_tuned_graph)):
         out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),
                      "alg_gbs": alg / (t * 1e-3) / 1e9}
     return out
@@ -187,6 +201,20 @@ def main():
     stream = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
 
+    for _ in range(args.warmup):
+        plan.solve(r, V, stream)
+    torch.cuda.synchronize()
+
+    # default tile schedules first, then the autotuner's choice (timed below)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        P.poisson_solve(plan.handle, r, V, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    untuned_ms = e0.elapsed_time(e1) / args.steps
+    plan.tune(r, V, stream=stream)
+    tile_sel, tile_lines = plan.schedule
     for _ in range(args.warmup):
         plan.solve(r, V, stream)
     torch.cuda.synchronize()
@@ -233,7 +261,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": list(n), "bc_mask": bc, "S": list(info["S"]),
                    "axis_order": list(info["axis_order"]), "h": H,
-                   "gaussians": WORKLOADS[args.workload]["gaussians"], "precision": "fp32"},
+                   "gaussians": WORKLOADS[args.workload]["gaussians"], "precision": "fp32",
+                   "tile_schedule": list(tile_sel), "tile_lines": list(tile_lines)},
+        "untuned_ms_per_step": untuned_ms,
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(PASS_NAMES[dom]) if args.workload == "free256"

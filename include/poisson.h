@@ -59,10 +59,15 @@ enum {
 
 enum { POISSON_FREE_X = 1, POISSON_FREE_Y = 2, POISSON_FREE_Z = 4 };
 
+/* Precision of the radix stages.  Data, twiddles, K^F and accumulation are
+ * float32 in every mode.  The split modes compute each radix-8 stage as a
+ * real 16x16 DFT matrix times 16 butterflies on the matrix cores, with the
+ * butterflies scaled by a power of two per butterfly and split into 16-bit
+ * parts whose cross products carry float32 accuracy. */
 enum {
-  POISSON_FP32 = 0,       /* float32 data, float32 arithmetic */
-  POISSON_SPLIT_FP16 = 1, /* reserved: radix stages on MFMA with fp16 hi+lo */
-  POISSON_SPLIT_BF16 = 2  /* reserved: radix stages on MFMA with bf16 splits */
+  POISSON_FP32 = 0,       /* all stages on the vector ALUs in float32 */
+  POISSON_SPLIT_FP16 = 1, /* radix-8 stages on MFMA: fp16 hi + lo, 3 products */
+  POISSON_SPLIT_BF16 = 2  /* radix-8 stages on MFMA: bf16 three-way split, 6 products */
 };
 
 /* Create a plan for an n1 x n2 x n3 grid with spacing h (> 0, finite).
@@ -146,14 +151,59 @@ int poisson_plan_destroy(poisson_plan_t plan);
 /* Batches of independent solves of different sizes and boundary conditions
  * (Section 5 motivates many densities per run).  n holds 3*count sizes,
  * bc_mask and h one entry per solve.  Solves with equal (n, bc_mask, h)
- * share one plan and one K^F. */
+ * share one plan and one K^F.  The batch owns one workspace: each plan's
+ * solves run in chunks of up to 64 whose intermediates fit a budget (96 MiB
+ * by default, or the environment variable POISSON_BATCH_CHUNK_MB read at
+ * creation), and every pass of a chunk is one kernel launch. */
 int poisson_batch_create(poisson_batch_t *out, int count, const int *n,
                          const unsigned *bc_mask, const double *h, int precision);
+/* Builds the default K^F of every distinct plan (as poisson_kernel_build). */
 int poisson_batch_kernel_build(poisson_batch_t batch, void *stream);
-/* rho_ptrs_dev / V_ptrs_dev: host arrays of `count` device pointers. */
+/* rho_ptrs / V_ptrs: host arrays of `count` device pointers, in creation
+ * order; solve i may be in place (rho_ptrs[i] == V_ptrs[i]).  Asynchronous,
+ * no allocation, no host sync: capturable into a HIP graph. */
 int poisson_batch_solve(poisson_batch_t batch, const float *const *rho_ptrs,
                         float *const *V_ptrs, void *stream);
 int poisson_batch_destroy(poisson_batch_t batch);
+
+/* Schedules and the autotuner.
+ *
+ * The radix decomposition of each FFT length is fixed.  Passes 0, 1, 3 and 4
+ * stage their lines through LDS in tiles of W consecutive lines; the tile
+ * schedule tile_sel = 0..3 asks for W of about 16, 8, 4 or 32 complex lines
+ * (0 is the default).  A schedule changes which lines a workgroup transforms
+ * together and how long its HBM row segments are, never a line's
+ * arithmetic: results are bitwise identical under every schedule.  Float32
+ * mode compiles every schedule that fits the LDS of a compute unit and is
+ * distinct from a lower one; split modes compile schedule 0 only.  Pass 2
+ * (the fused convolution) has no tile schedule (always 0). */
+
+/* Set the five passes' tile schedules.  POISSON_E_UNSUPPORTED if one is not
+ * compiled for its pass (then nothing changes). */
+int poisson_plan_set_schedule(poisson_plan_t plan, const int tile_sel[5]);
+
+/* Current schedules and, per pass, the complex lines per tile they give
+ * (0 for pass 2).  Either pointer may be NULL. */
+int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lines[5]);
+
+/* Autotuner: times every compiled tile schedule of every pass on this
+ * device (reps launches per candidate after a warm-up, best of two rounds,
+ * hipEvents on `stream`) and keeps the fastest; a candidate replaces the
+ * current choice only if at least 1% faster.  Runs solves on rho_dev and
+ * V_dev: V_dev (and the workspace) receive scratch values.  pass_ms (may
+ * be NULL) receives the chosen schedule's time per pass.  reps <= 0 means
+ * 10.  Needs K^F and a workspace; synchronous. */
+int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, int reps,
+                      double pass_ms[5], void *stream);
+
+/* Autotuner for a batch: tunes each distinct plan's tile schedules on its
+ * first chunk, then times whole batch solves for intermediates budgets of
+ * 32..256 MiB and keeps the fastest (chunk_mb, may be NULL, receives it).
+ * The arrays are those of poisson_batch_solve; V receives scratch values.
+ * May reallocate the batch workspace (graphs captured before then must be
+ * captured again).  reps <= 0 means 5.  Synchronous. */
+int poisson_batch_tune(poisson_batch_t batch, const float *const *rho_ptrs, float *const *V_ptrs,
+                       int reps, double *chunk_mb, void *stream);
 
 /* Residual check in float64 on the device: *out = ||v - ref||_2 / ||ref||_2
  * over `count` values, v float32 and ref float64, both device pointers.

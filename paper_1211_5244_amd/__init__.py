@@ -19,12 +19,14 @@ from ._lib import (  # noqa: F401
     POISSON_FREE_Z,
     POISSON_SPLIT_BF16,
     POISSON_SPLIT_FP16,
+    TILE_SCHEDULES,
     PoissonError,
     load_library,
     poisson_batch_create,
     poisson_batch_destroy,
     poisson_batch_kernel_build,
     poisson_batch_solve,
+    poisson_batch_tune,
     poisson_kernel_build,
     poisson_kernel_get,
     poisson_kernel_set,
@@ -32,7 +34,10 @@ from ._lib import (  # noqa: F401
     poisson_plan,
     poisson_plan_describe,
     poisson_plan_destroy,
+    poisson_plan_get_schedule,
     poisson_plan_rows,
+    poisson_plan_set_schedule,
+    poisson_plan_tune,
     poisson_rel_l2,
     poisson_set_workspace,
     poisson_solve,
@@ -85,6 +90,26 @@ class Plan:
         poisson_solve(self.handle, rho, V, stream)
         return V
 
+    @property
+    def schedule(self):
+        """Per-pass tile schedules (tile_sel[5], complex lines per tile[5])."""
+        return poisson_plan_get_schedule(self.handle)
+
+    def set_schedule(self, tile_sel):
+        poisson_plan_set_schedule(self.handle, tile_sel)
+
+    def tune(self, rho, V=None, reps=0, stream=None):
+        """Autotune the tile schedules on this device (V receives scratch
+        values); returns the chosen schedule's ms per pass."""
+        import torch
+        _check_grid(rho, self.n, "rho")
+        if V is None:
+            V = torch.empty_like(rho)
+        _check_grid(V, self.n, "V")
+        if stream is None:
+            stream = torch.cuda.current_stream(rho.device)
+        return poisson_plan_tune(self.handle, rho, V, reps, stream)
+
     def close(self):
         if getattr(self, "handle", None):
             poisson_plan_destroy(self.handle)
@@ -113,6 +138,17 @@ class Batch:
         if stream is None:
             stream = torch.cuda.current_stream(rho_list[0].device)
         poisson_batch_solve(self.handle, rho_list, V_list, stream)
+
+    def tune(self, rho_list, V_list, reps=0, stream=None):
+        """Autotune tile schedules and the per-launch budget (V receives
+        scratch values); returns the chosen budget in MiB."""
+        import torch
+        for i, (r, v) in enumerate(zip(rho_list, V_list)):
+            _check_grid(r, self.n_list[i], f"rho[{i}]")
+            _check_grid(v, self.n_list[i], f"V[{i}]")
+        if stream is None:
+            stream = torch.cuda.current_stream(rho_list[0].device)
+        return poisson_batch_tune(self.handle, rho_list, V_list, reps, stream)
 
     def close(self):
         if getattr(self, "handle", None):

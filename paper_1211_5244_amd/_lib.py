@@ -32,8 +32,13 @@ EXPORTED = (
     "poisson_kernel_set", "poisson_kernel_build", "poisson_kernel_get", "poisson_solve",
     "poisson_solve_passes",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
-    "poisson_batch_solve", "poisson_batch_destroy", "poisson_rel_l2", "poisson_last_error",
+    "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
+    "poisson_plan_get_schedule", "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2",
+    "poisson_last_error",
 )
+
+# tile schedules per pass (poisson_plan_set_schedule)
+TILE_SCHEDULES = 4
 
 
 class PoissonError(RuntimeError):
@@ -77,6 +82,11 @@ def load_library(path=None):
         "poisson_batch_kernel_build": (_i, [_vp, _vp]),
         "poisson_batch_solve": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
         "poisson_batch_destroy": (_i, [_vp]),
+        "poisson_plan_set_schedule": (_i, [_vp, ctypes.POINTER(_i)]),
+        "poisson_plan_get_schedule": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "poisson_plan_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+        "poisson_batch_tune": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
+                                    ctypes.POINTER(_d), _vp]),
         "poisson_rel_l2": (_i, [_vp, _vp, _sz, ctypes.POINTER(_d), _vp]),
         "poisson_last_error": (ctypes.c_char_p, []),
     }
@@ -205,3 +215,33 @@ def poisson_rel_l2(v, ref, count, stream=None):
     out = _d()
     _check(load_library().poisson_rel_l2(_ptr(v), _ptr(ref), count, ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def poisson_plan_set_schedule(plan, tile_sel):
+    arr = (_i * 5)(*[int(x) for x in tile_sel])
+    _check(load_library().poisson_plan_set_schedule(plan, arr))
+
+
+def poisson_plan_get_schedule(plan):
+    """(tile_sel[5], tile_lines[5])"""
+    sel = (_i * 5)()
+    lines = (_i * 5)()
+    _check(load_library().poisson_plan_get_schedule(plan, sel, lines))
+    return tuple(sel), tuple(lines)
+
+
+def poisson_plan_tune(plan, rho, V, reps=0, stream=None):
+    """Returns the chosen schedule's time per pass in ms."""
+    ms = (_d * 5)()
+    _check(load_library().poisson_plan_tune(plan, _ptr(rho), _ptr(V), int(reps), ms, _stream(stream)))
+    return tuple(ms)
+
+
+def poisson_batch_tune(batch, rho_list, V_list, reps=0, stream=None):
+    """Returns the chosen intermediates budget per launch in MiB."""
+    count = len(rho_list)
+    r = (_vp * count)(*[_ptr(x) for x in rho_list])
+    v = (_vp * count)(*[_ptr(x) for x in V_list])
+    mb = _d()
+    _check(load_library().poisson_batch_tune(batch, r, v, int(reps), ctypes.byref(mb), _stream(stream)))
+    return mb.value

@@ -78,6 +78,7 @@ struct poisson_batch_s {
   std::vector<int> which;                   // solve i uses plans[which[i]]
   std::vector<std::vector<int>> members;    // per plan: its solves, in order
   std::vector<int> chunk;                   // per plan: solves per launch
+  double chunk_mb = 96.0;                   // intermediates budget of one launch
   void *ws = nullptr;                       // shared by all chunks (one stream)
   size_t ws_bytes = 0;
   int device = 0;
@@ -135,6 +136,26 @@ std::vector<double> cosine_table(int S) {
   const long double two_pi = 6.283185307179586476925286766559L;
   for (int n = 0; n < S; ++n) t[n] = double(std::cos(two_pi * n / S));
   return t;
+}
+
+// Solves per launch for each plan of B under an intermediates budget of
+// budget_mb MiB (at least 1, at most kMaxBatch); returns the workspace the
+// largest chunk needs.
+size_t batch_chunks(poisson_batch_t B, double budget_mb, std::vector<int> &chunk) {
+  const size_t budget = size_t(budget_mb * 1024.0 * 1024.0);
+  size_t ws = 0;
+  chunk.clear();
+  for (size_t u = 0; u < B->plans.size(); ++u) {
+    const size_t per = B->plans[u]->g.ws_bytes;
+    size_t c = per > 0 ? budget / per : 1;
+    if (c < 1) c = 1;
+    if (c > size_t(psn::kMaxBatch)) c = psn::kMaxBatch;
+    if (c > B->members[u].size()) c = B->members[u].size();
+    chunk.push_back(int(c));
+    ws = std::max(ws, c * per);
+  }
+  B->chunk_mb = budget_mb;
+  return ws;
 }
 
 int finish_kernel(poisson_plan_t P, hipStream_t s) {
@@ -436,23 +457,13 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n, const un
     // Solves per launch: as many as keep a chunk's intermediates within the
     // budget (default 96 MiB, below the 256 MB Infinity Cache, so the five
     // passes of a chunk re-read their intermediates from cache), at most
-    // kMaxBatch.
+    // kMaxBatch.  poisson_batch_tune may pick another budget.
     double budget_mb = 96.0;
     if (const char *env = std::getenv("POISSON_BATCH_CHUNK_MB")) {
       const double v = std::atof(env);
       if (v > 0) budget_mb = v;
     }
-    const size_t budget = size_t(budget_mb * 1024.0 * 1024.0);
-    for (size_t u = 0; u < B->plans.size(); ++u) {
-      const size_t per = B->plans[u]->g.ws_bytes;
-      size_t c = per > 0 ? budget / per : 1;
-      if (c < 1) c = 1;
-      if (c > size_t(psn::kMaxBatch)) c = psn::kMaxBatch;
-      if (c > B->members[u].size()) c = B->members[u].size();
-      B->chunk.push_back(int(c));
-      const size_t need = c * per;
-      if (need > B->ws_bytes) B->ws_bytes = need;
-    }
+    B->ws_bytes = batch_chunks(B, budget_mb, B->chunk);
     hipError_t e = hipMalloc(&B->ws, B->ws_bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -512,6 +523,174 @@ int poisson_batch_destroy(poisson_batch_t B) {
   }
   for (auto *P : B->plans) poisson_plan_destroy(P);
   delete B;
+  return POISSON_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+
+int poisson_plan_set_schedule(poisson_plan_t P, const int tile_sel[5]) {
+  if (!P || !tile_sel) return fail(POISSON_E_ARG, "NULL argument");
+  for (int k = 0; k < 5; ++k) {
+    if (tile_sel[k] < 0 || tile_sel[k] >= psn::kTileSchedules)
+      return fail(POISSON_E_ARG, "tile schedule out of range");
+    if (k == psn::KIND_CONV ? tile_sel[k] != 0
+                            : psn::pass_tile_lines(P->g.pass[k], tile_sel[k], P->precision) == 0)
+      return fail(POISSON_E_UNSUPPORTED,
+                  "tile schedule " + std::to_string(tile_sel[k]) + " is not compiled for pass " +
+                      std::to_string(k) + " of this plan");
+  }
+  for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = tile_sel[k];
+  return POISSON_OK;
+}
+
+int poisson_plan_get_schedule(poisson_plan_t P, int tile_sel[5], int tile_lines[5]) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  for (int k = 0; k < 5; ++k) {
+    const psn::Pass &pass = P->g.pass[k];
+    if (tile_sel) tile_sel[k] = pass.tile_sel;
+    if (tile_lines)
+      tile_lines[k] = k == psn::KIND_CONV ? 0 : psn::pass_tile_lines(pass, pass.tile_sel, P->precision);
+  }
+  return POISSON_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Best (over two rounds) mean time in ms of one `enqueue()` over `reps`
+// back-to-back calls on stream s, after one warm-up call.
+template <typename F> int time_enqueue(F &&enqueue, hipStream_t s, int reps, double *ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PSN_TRY_HIP(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  double best = INFINITY;
+  int rc = enqueue();
+  for (int round = 0; round < 2 && rc == POISSON_OK; ++round) {
+    e = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && rc == POISSON_OK && e == hipSuccess; ++i) rc = enqueue();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess && rc == POISSON_OK) rc = hip_fail(e, "timing events");
+    if (rc == POISSON_OK) best = std::min(best, double(t) / reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return rc;
+}
+
+// Picks each pass's fastest tile schedule for `count` solves of plan P run
+// together (arrays rho/V, intermediates in ws).  A schedule replaces the
+// current choice only when it is at least 1% faster.
+int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float *const *V,
+                     void *ws, hipStream_t s, int reps, double *pass_ms) {
+  int rc = enqueue_passes(P, count, rho, V, ws, 0, 4, s);  // every pass reads written data
+  if (rc) return rc;
+  for (int k = 0; k < 5; ++k) {
+    psn::Pass &pass = P->g.pass[k];
+    const int keep = pass.tile_sel;
+    int best_ts = -1;
+    double best = INFINITY;
+    for (int ts = 0; ts < psn::kTileSchedules; ++ts) {
+      if (k == psn::KIND_CONV ? ts != 0 : psn::pass_tile_lines(pass, ts, P->precision) == 0) continue;
+      pass.tile_sel = ts;
+      double t = 0;
+      rc = time_enqueue([&] { return enqueue_passes(P, count, rho, V, ws, k, k, s); }, s, reps, &t);
+      if (rc) {
+        pass.tile_sel = keep;
+        return rc;
+      }
+      if (best_ts < 0 || t < 0.99 * best) {
+        best = t;
+        best_ts = ts;
+      }
+    }
+    pass.tile_sel = best_ts < 0 ? 0 : best_ts;
+    if (pass_ms) pass_ms[k] = best;
+  }
+  return POISSON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int poisson_plan_tune(poisson_plan_t P, const float *rho, float *V, int reps, double pass_ms[5],
+                      void *stream) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  if (!rho || !V) return fail(POISSON_E_ARG, "rho or V is NULL");
+  if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "no K^F has been set or built");
+  if (!P->ws) return fail(POISSON_E_STATE, "no workspace");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  if (reps <= 0) reps = 10;
+  return tune_plan_passes(P, 1, &rho, &V, P->ws, static_cast<hipStream_t>(stream), reps, pass_ms);
+}
+
+int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const *V, int reps,
+                       double *chunk_mb, void *stream) {
+  if (!B || !rho || !V) return fail(POISSON_E_ARG, "NULL argument");
+  for (size_t i = 0; i < B->which.size(); ++i)
+    if (!rho[i] || !V[i]) return fail(POISSON_E_ARG, "batch entry " + std::to_string(i) + ": NULL pointer");
+  for (auto *P : B->plans)
+    if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "batch kernels not built");
+  DeviceScope ds(B->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the batch's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (reps <= 0) reps = 5;
+  // 1. tile schedules of every plan, timed on its first chunk
+  std::vector<const float *> r(psn::kMaxBatch);
+  std::vector<float *> v(psn::kMaxBatch);
+  for (size_t u = 0; u < B->plans.size(); ++u) {
+    const std::vector<int> &m = B->members[u];
+    const int cnt = std::min(int(m.size()), B->chunk[u]);
+    for (int j = 0; j < cnt; ++j) {
+      r[j] = rho[m[j]];
+      v[j] = V[m[j]];
+    }
+    int rc = tune_plan_passes(B->plans[u], cnt, r.data(), v.data(), B->ws, s, reps, nullptr);
+    if (rc) return rc;
+  }
+  // 2. the intermediates budget of one launch, timed on the whole batch
+  std::vector<double> budgets = {B->chunk_mb};  // the current budget first
+  for (double mb : {32.0, 64.0, 96.0, 128.0, 192.0, 256.0})
+    if (mb != B->chunk_mb) budgets.push_back(mb);
+  double best_mb = B->chunk_mb, best = INFINITY;
+  {
+    for (double mb : budgets) {
+      std::vector<int> chunk;
+      const size_t need = batch_chunks(B, mb, chunk);
+      if (need > B->ws_bytes) {
+        PSN_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          continue;  // a budget that does not fit is not a candidate
+        }
+        (void)hipFree(B->ws);
+        B->ws = p;
+        B->ws_bytes = need;
+      }
+      B->chunk = chunk;
+      double t = 0;
+      int rc = time_enqueue([&] { return poisson_batch_solve(B, rho, V, stream); }, s, reps, &t);
+      if (rc) return rc;
+      if (t < 0.99 * best) {
+        best = t;
+        best_mb = mb;
+      }
+    }
+  }
+  (void)batch_chunks(B, best_mb, B->chunk);
+  if (chunk_mb) *chunk_mb = best_mb;
   return POISSON_OK;
 }
 

@@ -29,6 +29,13 @@ struct PassIO {
 hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
                        int S_q, int mode, hipStream_t stream);
 
+// Tile schedules of the tiled passes (P.tile_sel = 0..kTileSchedules-1).
+// Complex lines per workgroup tile that schedule ts gives pass P in `mode`,
+// or 0 where that schedule is not compiled (it then runs as schedule 0).
+// The conv pass has no tile schedule (always 0).
+constexpr int kTileSchedules = 4;
+int pass_tile_lines(const Pass &P, int ts, int mode);
+
 // float64 K^F octant of the default Green's function (layout of the C ABI:
 // k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.
 // cos_tabs[j]: device table cos(2 pi n / S_j), n = 0..S_j-1, for each axis.

@@ -29,6 +29,8 @@
 // imaginary part line b.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_core.h"
 #include "fft_split.h"
 #include "kernels.h"
@@ -38,6 +40,85 @@ namespace psn {
 template <int L, int MODE>
 hipError_t launch_for_mode(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
                            int S_q, hipStream_t s);
+
+template <int A, int B> constexpr int cmax() { return A > B ? A : B; }
+
+// Tile schedules of the tiled passes: schedule TS stages tiles of about
+// tile_lines(TS) complex lines (16, 8, 4 or 32) per workgroup.  The lines of
+// a tile are the W consecutive lines whose elements form the contiguous row
+// segments on the tiled side, so TS trades row-segment length (bytes per HBM
+// request) against workgroup size and LDS.  Every schedule computes each
+// line's transform with the same arithmetic: results do not depend on it.
+constexpr int tile_lines(int ts) { return ts == 1 ? 8 : ts == 2 ? 4 : ts == 3 ? 32 : 16; }
+
+// Workgroup geometry for length L: NW waves of LPW line groups of T lanes.
+template <int L, int TS = 0> struct Geo {
+  static constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T;
+  static constexpr int NW_WANT = tile_lines(TS) / LPW;
+  static constexpr int NW = NW_WANT < 1 ? 1 : NW_WANT > 16 ? 16 : NW_WANT;
+  static constexpr int NT = NW * 64;
+  static constexpr int G = NW * LPW;  // complex lines in flight per workgroup
+  static constexpr int SLOTS = line_lds_slots<L>();
+  static constexpr int XCH_F2 = G * SLOTS;
+};
+
+// LDS (float2 slots) of each tiled kernel; a schedule is compiled only where
+// it fits the 160 KiB of a CDNA4 compute unit.
+constexpr int kLdsLimitF2 = 160 * 1024 / 8;
+template <int L, int TS> constexpr int c2c_lds_f2() {
+  using C = Geo<L, TS>;
+  return C::XCH_F2 > (L + 1) * (C::G + 1) ? C::XCH_F2 : (L + 1) * (C::G + 1);
+}
+template <int L, int TS, bool PAD> constexpr int r2c_lds_f2() {
+  using C = Geo<L, TS>;
+  constexpr int W = 2 * C::G, LDR = W + 2, LDC = W + 1;
+  constexpr int ROWS_IN = PAD ? L / 2 : L, ROWS_OUT = L / 2 + 1;
+  return cmax<cmax<C::XCH_F2, ROWS_OUT * LDC>(), (ROWS_IN * LDR + 1) / 2>();
+}
+template <int L, int TS, bool CROP> constexpr int c2r_lds_f2() {
+  using C = Geo<L, TS>;
+  constexpr int W = 2 * C::G, LDR = W + 2, LDC = W + 1;
+  constexpr int ROWS_IN = L / 2 + 1, ROWS_OUT = CROP ? L / 2 : L;
+  return cmax<cmax<C::XCH_F2, ROWS_IN * LDC>(), (ROWS_OUT * LDR + 1) / 2>();
+}
+
+// A schedule is compiled only if its tile width differs from every lower
+// schedule's (a clamped schedule would duplicate one).
+template <int L, int TS> constexpr bool tile_distinct() {
+  if constexpr (TS == 0) return true;
+  else if constexpr (TS == 1) return Geo<L, 1>::G != Geo<L, 0>::G;
+  else if constexpr (TS == 2)
+    return Geo<L, 2>::G != Geo<L, 0>::G && Geo<L, 2>::G != Geo<L, 1>::G;
+  else
+    return Geo<L, 3>::G != Geo<L, 0>::G && Geo<L, 3>::G != Geo<L, 1>::G &&
+           Geo<L, 3>::G != Geo<L, 2>::G;
+}
+
+// Complex lines per tile that schedule ts gives pass P at length L in float32
+// mode (0 if the schedule does not fit; split modes run schedule 0 only).
+template <int L> int tile_lines_of(const Pass &P, int ts) {
+  auto pick = [&](auto tsc) -> int {
+    constexpr int T = decltype(tsc)::value;
+    bool fits = true;
+    switch (P.kind) {
+      case KIND_FWD:
+      case KIND_INV: fits = c2c_lds_f2<L, T>() <= kLdsLimitF2; break;
+      case KIND_R2C: fits = P.pad ? r2c_lds_f2<L, T, true>() <= kLdsLimitF2
+                                  : r2c_lds_f2<L, T, false>() <= kLdsLimitF2; break;
+      case KIND_C2R: fits = P.crop ? c2r_lds_f2<L, T, true>() <= kLdsLimitF2
+                                   : c2r_lds_f2<L, T, false>() <= kLdsLimitF2; break;
+      default: return 0;
+    }
+    return fits && tile_distinct<L, T>() ? Geo<L, T>::G : 0;
+  };
+  switch (ts) {
+    case 0: return pick(std::integral_constant<int, 0>{});
+    case 1: return pick(std::integral_constant<int, 1>{});
+    case 2: return pick(std::integral_constant<int, 2>{});
+    case 3: return pick(std::integral_constant<int, 3>{});
+  }
+  return 0;
+}
 
 #if !defined(PSN_DISPATCH_ONLY)
 
@@ -56,17 +137,6 @@ struct PassParams {
   int ntiles;
 };
 
-// Workgroup geometry for length L: NW waves of LPW line groups of T lanes.
-template <int L> struct Geo {
-  static constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T;
-  static constexpr int NW = LPW >= 16 ? 1 : 16 / LPW;
-  static constexpr int NT = NW * 64;
-  static constexpr int G = NW * LPW;  // complex lines in flight per workgroup
-  static constexpr int SLOTS = line_lds_slots<L>();
-  static constexpr int XCH_F2 = G * SLOTS;
-};
-
-template <int A, int B> constexpr int cmax() { return A > B ? A : B; }
 
 // The line transform of a kernel: float32 radix stages on the vector ALUs
 // (MODE_FP32), or radix-8 stages as split-precision DFT matmuls on the
@@ -161,13 +231,13 @@ __device__ __forceinline__ TileCoord tile_coord(const PassParams &a, int tile, i
 }
 
 // ------------------------------------------------------------- P2 / P4
-template <int L, bool INV, bool IN_TILED, bool OUT_TILED, bool PC, int MODE>
-__global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
-  using C = Geo<L>;
+template <int L, bool INV, bool IN_TILED, bool OUT_TILED, bool PC, int MODE, int TS>
+__global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
+  using C = Geo<L, TS>;
   constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = C::G, LD = W + 1;
   constexpr bool PAD = !INV && PC, CROP = INV && PC;
   constexpr int ROWS_IN = PAD ? L / 2 : L, ROWS_OUT = CROP ? L / 2 : L;
-  constexpr int LDS_F2 = cmax<C::XCH_F2, (L + 1) * LD>();
+  constexpr int LDS_F2 = c2c_lds_f2<L, TS>();
   __shared__ float2 smem[LDS_F2];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -240,13 +310,13 @@ __global__ __launch_bounds__(Geo<L>::NT) void c2c_kernel(PassParams a) {
 }
 
 // ------------------------------------------------------------------ P1
-template <int L, bool IN_TILED, bool PAD, int MODE>
-__global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
-  using C = Geo<L>;
+template <int L, bool IN_TILED, bool PAD, int MODE, int TS>
+__global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
+  using C = Geo<L, TS>;
   constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = 2 * C::G;
   constexpr int LDR = W + 2, LDC = W + 1;  // real tile (floats), complex tile (float2)
   constexpr int ROWS_IN = PAD ? L / 2 : L, ROWS_OUT = L / 2 + 1;
-  constexpr int LDS_F2 = cmax<cmax<C::XCH_F2, ROWS_OUT * LDC>(), (ROWS_IN * LDR + 1) / 2>();
+  constexpr int LDS_F2 = r2c_lds_f2<L, TS, PAD>();
   __shared__ float2 smem[LDS_F2];
   float *smem_f = reinterpret_cast<float *>(smem);
 
@@ -338,13 +408,13 @@ __global__ __launch_bounds__(Geo<L>::NT) void r2c_kernel(PassParams a) {
 }
 
 // ------------------------------------------------------------------ P5
-template <int L, bool OUT_TILED, bool CROP, int MODE>
-__global__ __launch_bounds__(Geo<L>::NT) void c2r_kernel(PassParams a) {
-  using C = Geo<L>;
+template <int L, bool OUT_TILED, bool CROP, int MODE, int TS>
+__global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
+  using C = Geo<L, TS>;
   constexpr int E = C::E, T = C::T, LPW = C::LPW, NT = C::NT, W = 2 * C::G;
   constexpr int LDR = W + 2, LDC = W + 1;
   constexpr int ROWS_IN = L / 2 + 1, ROWS_OUT = CROP ? L / 2 : L;
-  constexpr int LDS_F2 = cmax<cmax<C::XCH_F2, ROWS_IN * LDC>(), (ROWS_OUT * LDR + 1) / 2>();
+  constexpr int LDS_F2 = c2r_lds_f2<L, TS, CROP>();
   __shared__ float2 smem[LDS_F2];
   float *smem_f = reinterpret_cast<float *>(smem);
 
@@ -582,38 +652,74 @@ int persistent_grid(K kernel, int threads, int ntiles) {
   return int(ntiles < cap ? ntiles : cap);
 }
 
-template <int L, int MODE, bool INV, bool IT, bool OT, bool PC>
-hipError_t launch_c2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
-  using C = Geo<L>;
+template <int L, int MODE, bool INV, bool IT, bool OT, bool PC, int TS>
+hipError_t launch_c2c_ts(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
+  using C = Geo<L, TS>;
   PassParams a = make_params(P, io, tw, C::G);
-  auto k = c2c_kernel<L, INV, IT, OT, PC, MODE>;
+  auto k = c2c_kernel<L, INV, IT, OT, PC, MODE, TS>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
+}
+
+template <int L, int MODE, bool IT, bool PAD, int TS>
+hipError_t launch_r2c_ts(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
+  using C = Geo<L, TS>;
+  PassParams a = make_params(P, io, tw, 2 * C::G);
+  auto k = r2c_kernel<L, IT, PAD, MODE, TS>;
+  const int grid = persistent_grid(k, C::NT, a.ntiles);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int L, int MODE, bool OT, bool CROP, int TS>
+hipError_t launch_c2r_ts(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
+  using C = Geo<L, TS>;
+  PassParams a = make_params(P, io, tw, 2 * C::G);
+  auto k = c2r_kernel<L, OT, CROP, MODE, TS>;
+  const int grid = persistent_grid(k, C::NT, a.ntiles);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+// The pass's tile schedule selects the kernel variant.  Only float32 mode
+// compiles the alternatives; a schedule that does not fit (or a split mode)
+// runs schedule 0.
+#define PSN_TILE_DISPATCH(LAUNCH, FITS, ...)                                   \
+  if constexpr (MODE == MODE_FP32) {                                           \
+    switch (P.tile_sel) {                                                      \
+      case 1: if constexpr (FITS(1)) return LAUNCH<__VA_ARGS__, 1>(P, io, tw, s); break; \
+      case 2: if constexpr (FITS(2)) return LAUNCH<__VA_ARGS__, 2>(P, io, tw, s); break; \
+      case 3: if constexpr (FITS(3)) return LAUNCH<__VA_ARGS__, 3>(P, io, tw, s); break; \
+      default: break;                                                          \
+    }                                                                          \
+  }                                                                            \
+  return LAUNCH<__VA_ARGS__, 0>(P, io, tw, s);
+
+template <int L, int MODE, bool INV, bool IT, bool OT, bool PC>
+hipError_t launch_c2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
+#define PSN_FITS(T) (c2c_lds_f2<L, T>() <= kLdsLimitF2 && tile_distinct<L, T>())
+  PSN_TILE_DISPATCH(launch_c2c_ts, PSN_FITS, L, MODE, INV, IT, OT, PC)
+#undef PSN_FITS
 }
 
 template <int L, int MODE, bool IT, bool PAD>
 hipError_t launch_r2c(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
-  using C = Geo<L>;
-  PassParams a = make_params(P, io, tw, 2 * C::G);
-  auto k = r2c_kernel<L, IT, PAD, MODE>;
-  const int grid = persistent_grid(k, C::NT, a.ntiles);
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
-  return hipGetLastError();
+#define PSN_FITS(T) (r2c_lds_f2<L, T, PAD>() <= kLdsLimitF2 && tile_distinct<L, T>())
+  PSN_TILE_DISPATCH(launch_r2c_ts, PSN_FITS, L, MODE, IT, PAD)
+#undef PSN_FITS
 }
 
 template <int L, int MODE, bool OT, bool CROP>
 hipError_t launch_c2r(const Pass &P, const PassIO &io, const float2 *tw, hipStream_t s) {
-  using C = Geo<L>;
-  PassParams a = make_params(P, io, tw, 2 * C::G);
-  auto k = c2r_kernel<L, OT, CROP, MODE>;
-  const int grid = persistent_grid(k, C::NT, a.ntiles);
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
-  return hipGetLastError();
+#define PSN_FITS(T) (c2r_lds_f2<L, T, CROP>() <= kLdsLimitF2 && tile_distinct<L, T>())
+  PSN_TILE_DISPATCH(launch_c2r_ts, PSN_FITS, L, MODE, OT, CROP)
+#undef PSN_FITS
 }
+#undef PSN_TILE_DISPATCH
 
 template <int L, int MODE, bool PC>
 hipError_t launch_conv(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
@@ -705,6 +811,20 @@ hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const 
 #undef PSN_CASE
   }
   return hipErrorInvalidValue;
+}
+
+int pass_tile_lines(const Pass &P, int ts, int mode) {
+  if (ts < 0 || ts >= kTileSchedules) return 0;
+  if (mode != MODE_FP32 && ts != 0) return 0;
+  switch (P.L) {
+#define PSN_CASE(LL) \
+  case LL: return tile_lines_of<LL>(P, ts);
+    PSN_CASE(4) PSN_CASE(6) PSN_CASE(8) PSN_CASE(12) PSN_CASE(16) PSN_CASE(24) PSN_CASE(32)
+    PSN_CASE(48) PSN_CASE(64) PSN_CASE(96) PSN_CASE(128) PSN_CASE(192) PSN_CASE(256)
+    PSN_CASE(384) PSN_CASE(512) PSN_CASE(768) PSN_CASE(1024)
+#undef PSN_CASE
+  }
+  return 0;
 }
 
 #endif  // PSN_DISPATCH_ONLY

@@ -29,6 +29,7 @@ struct Pass {
   bool in_tiled = false, out_tiled = false;
   bool pad = false;   // input holds L/2 values (free axis before its transform)
   bool crop = false;  // only the first L/2 outputs are kept (free axis after inverse)
+  int tile_sel = 0;   // tile schedule of a tiled pass (0 = default; see the autotuner)
 };
 
 struct Geometry {

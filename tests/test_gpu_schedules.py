@@ -1,0 +1,138 @@
+"""GPU: tile schedules and the autotuner.
+
+A tile schedule only changes which lines a workgroup stages together, so
+every compiled schedule must give results bitwise equal to schedule 0 (whose
+parity against the oracle the parity tests establish), on regular and ragged
+tiles.  The autotuner must leave a valid schedule and equal results.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1211_5244_amd as P
+from densities import batch_density, draw_gaussians, gaussian_mixture
+
+pytestmark = pytest.mark.gpu
+
+H = 0.3
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.load_library()
+    return torch
+
+
+def _rho(torch, n, bc, seed):
+    gs = draw_gaussians(n, H, 5, (1.0, 3.0), seed)
+    return torch.from_numpy(gaussian_mixture(n, bc, H, gs).astype(np.float32)).cuda()
+
+
+def _compiled(plan):
+    """Per pass, the schedules compiled for it (distinct tile widths)."""
+    out = []
+    for k in range(5):
+        ok = []
+        for ts in range(P.TILE_SCHEDULES):
+            sel = [0] * 5
+            sel[k] = ts
+            try:
+                plan.set_schedule(sel)
+                ok.append(ts)
+            except P.PoissonError as e:
+                assert e.code == P._lib.POISSON_E_UNSUPPORTED, e
+        out.append(ok)
+    plan.set_schedule([0] * 5)
+    return out
+
+
+# (n, bc): 512-length lines, ragged tiles (extents not multiples of the tile
+# width), mixed radix, all four boundary classes
+CASES = [((256, 256, 256), 7), ((24, 48, 12), 7), ((48, 24, 64), 3), ((12, 48, 24), 2),
+         ((32, 24, 48), 0), ((96, 64, 48), 5)]
+
+
+@pytest.mark.parametrize("n,bc", CASES)
+def test_every_tile_schedule_is_bitwise_equal(torch_dev, n, bc):
+    torch = torch_dev
+    r = _rho(torch, n, bc, seed=700 + bc)
+    plan = P.Plan(n, bc, H)
+    ref = plan.solve(r).clone()
+    compiled = _compiled(plan)
+    print(f"{n} bc={bc}: compiled schedules per pass {compiled}", flush=True)
+    assert compiled[2] == [0]  # the fused conv pass has no tile schedule
+    assert all(0 in c for c in compiled)
+    # one pass at a time, then all passes together
+    trials = []
+    for k in range(5):
+        for ts in compiled[k][1:]:
+            sel = [0] * 5
+            sel[k] = ts
+            trials.append(sel)
+    for ts in range(1, P.TILE_SCHEDULES):  # every pass on schedule ts where compiled
+        trials.append([ts if ts in c else 0 for c in compiled])
+    for sel in trials:
+        plan.set_schedule(sel)
+        got_sel, lines = plan.schedule
+        assert list(got_sel) == sel
+        assert lines[2] == 0 and all(lines[k] > 0 for k in (0, 1, 3, 4))
+        V = plan.solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(V, ref), (n, bc, sel)
+
+
+def test_schedule_rejects_bad_values(torch_dev):
+    plan = P.Plan((32, 32, 32), 7, H)
+    with pytest.raises(P.PoissonError) as e:
+        plan.set_schedule([P.TILE_SCHEDULES, 0, 0, 0, 0])
+    assert e.value.code == P._lib.POISSON_E_ARG
+    with pytest.raises(P.PoissonError) as e:
+        plan.set_schedule([0, 0, 1, 0, 0])
+    assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
+    assert list(plan.schedule[0]) == [0] * 5  # unchanged after a rejected call
+    split = P.Plan((32, 32, 32), 7, H, precision=P.POISSON_SPLIT_FP16)
+    with pytest.raises(P.PoissonError) as e:
+        split.set_schedule([1, 0, 0, 0, 0])
+    assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,bc", [((256, 256, 256), 7), ((64, 96, 48), 3)])
+def test_tune_keeps_results(torch_dev, n, bc):
+    torch = torch_dev
+    r = _rho(torch, n, bc, seed=800 + bc)
+    plan = P.Plan(n, bc, H)
+    ref = plan.solve(r).clone()
+    scratch = torch.empty_like(r)
+    ms = plan.tune(r, scratch, reps=3)
+    sel, lines = plan.schedule
+    print(f"{n} bc={bc}: tuned {sel} lines {lines} ms {[round(x, 4) for x in ms]}", flush=True)
+    assert all(np.isfinite(ms)) and all(x > 0 for x in ms)
+    V = plan.solve(r)
+    torch.cuda.synchronize()
+    assert torch.equal(V, ref)
+    if n == (64, 96, 48):
+        err = oracle.rel_l2(V.cpu().numpy(), oracle.solve(r.cpu().numpy().astype(np.float64), bc, H))
+        assert err <= 1e-6
+
+
+def test_batch_tune_keeps_results(torch_dev):
+    torch = torch_dev
+    rng = np.random.default_rng(4999)
+    cases = [((int(e),) * 3, int(b), 9000 + i)
+             for i, (e, b) in enumerate(zip(rng.choice([32, 48, 64], 24), rng.choice([0, 3, 5, 7], 24)))]
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases))
+    ref = [torch.empty_like(r) for r in rhos]
+    B.solve(rhos, ref)
+    scratch = [torch.empty_like(r) for r in rhos]
+    mb = B.tune(rhos, scratch, reps=2)
+    print(f"batch tune: {mb} MiB per launch", flush=True)
+    assert mb in (32.0, 64.0, 96.0, 128.0, 192.0, 256.0)
+    Vs = [torch.empty_like(r) for r in rhos]
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for i in range(len(cases)):
+        assert torch.equal(Vs[i], ref[i]), (i, cases[i])
