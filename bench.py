@@ -59,13 +59,14 @@ def measured_traffic(kernel):
     return None
 
 
-def cpu_baseline(rho32, n, bc, reps=3):
+def cpu_baseline(rho32, n, bc, reps=3, workers=None, warmup=True):
     """The FP64 oracle on this host, K^F prebuilt (as the GPU's is)."""
     import oracle
     rho64 = rho32.astype(np.float64)
     kf = oracle.kernel_fourier(n, bc, H)
-    workers = os.cpu_count() or 1
-    oracle.solve(rho64, bc, H, kf=kf, workers=workers)  # warm-up
+    workers = workers or os.cpu_count() or 1
+    if warmup:
+        oracle.solve(rho64, bc, H, kf=kf, workers=workers)
     t = []
     for _ in range(reps):
         t0 = time.perf_counter()
@@ -73,7 +74,8 @@ def cpu_baseline(rho32, n, bc, reps=3):
         t.append(time.perf_counter() - t0)
     med = float(np.median(t))
     return V, {"value": 1.0 / med, "unit": "solves/s", "cores": workers, "kind": "oracle",
-               "sample": f"{reps} whole FP64 solves of the same workload after 1 warm-up "
+               "sample": f"{reps} whole FP64 solves of the same workload"
+                         f"{' after 1 warm-up' if warmup else ''} "
                          f"(scipy.fft, workers={workers}, K^F prebuilt); median {med:.3f} s"}
 
 
@@ -238,6 +240,8 @@ def main():
     torch.cuda.synchronize()
     per_pass = [float(np.mean([ev[k][p].elapsed_time(ev[k][p + 1]) for k in range(args.steps)]))
                 for p in range(5)]
+    step_ms = np.array([ev[k][0].elapsed_time(ev[k][5]) for k in range(args.steps)])
+    step_pct = {f"p{q}": float(np.percentile(step_ms, q)) for q in (10, 50, 90)}
 
     V_gpu = V.cpu().numpy()
     copy_gbs = copy_bandwidth(torch, dev)
@@ -275,6 +279,7 @@ def main():
         "copy_gbs": copy_gbs,
         "solve_vs_copy": solve_gbs / copy_gbs,
         "passes_ms": dict(zip(PASS_NAMES, per_pass)),
+        "step_ms_percentiles": step_pct,  # per solve, from the per-pass event loop
         "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
     }
     # split-precision modes on the same workload: time and accuracy
@@ -303,6 +308,9 @@ def main():
     if not args.no_cpu_baseline:
         V_ref, cb = cpu_baseline(rho32, n, bc)
         out["cpu_baseline"] = cb
+        # one core, as the paper's single-core CPU comparison
+        _, cb1 = cpu_baseline(rho32, n, bc, reps=1, workers=1, warmup=False)
+        out["cpu_baseline_1core"] = cb1
         diff = V_gpu.astype(np.float64) - V_ref
         out["rel_l2_vs_oracle"] = float(np.linalg.norm(diff) / np.linalg.norm(V_ref))
         for name, rec in out.get("split", {}).items():
