@@ -167,6 +167,52 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     return out
 
 
+def fig1(torch, P, dev, steps, warmup):
+    """Figure 1's experiment (Section 4): time of each BC class relative to the
+    fully periodic solve of the same FFT size S^3, with Section 3's axis-order
+    study (wire with its periodic axis last, surface with its free axis
+    first) and the row-count prediction of each.  Timing does not depend on
+    the density's values: each case solves a seeded normal field."""
+    stream = torch.cuda.current_stream(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    out = []
+    for S in (64, 128, 256, 512):
+        N = S // 2
+        cases = [("periodic", (S, S, S), 0, None),
+                 ("free", (N, N, N), 7, None),
+                 ("wire", (N, N, S), 3, None),                      # z periodic, first
+                 ("wire_periodic_last", (N, N, S), 3, (0, 1, 2)),
+                 ("surface", (S, N, S), 2, None),                   # y free, last
+                 ("surface_free_first", (S, N, S), 2, (1, 0, 2))]
+        base = None
+        for name, n, bc, order in cases:
+            plan = P.Plan(n, bc, H, axis_order=order)
+            d = P.poisson_plan_describe_ordered(*n, bc, axis_order=plan.info["axis_order"])
+            work = sum(rw * d["S"][a] for rw, a in zip(d["rows"], d["axis_order"]))
+            r = torch.randn((n[2], n[1], n[0]), generator=g, device=dev, dtype=torch.float32)
+            V = torch.empty_like(r)
+            for _ in range(warmup):
+                plan.solve(r, V, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                P.poisson_solve(plan.handle, r, V, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            if name == "periodic":
+                base = (ms, work, d["alg_bytes"])
+            out.append({"S": S, "case": name, "n": list(n), "bc_mask": bc,
+                        "axis_order": list(d["axis_order"]), "ms": ms,
+                        "time_vs_periodic": ms / base[0],
+                        "fft_work_vs_periodic": work / base[1],
+                        "alg_bytes_vs_periodic": d["alg_bytes"] / base[2]})
+            plan.close()
+            del r, V
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +224,9 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision modes")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy (counter calibration)")
+    ap.add_argument("--fig1", action="store_true",
+                    help="only run the per-BC timing relative to periodic (Figure 1) and the "
+                         "axis-order study")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -192,6 +241,13 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_only:
         print(json.dumps({"copy_gbs": copy_bandwidth(torch, dev)}), flush=True)
+        return
+    if args.fig1:
+        P.load_library()
+        rows = fig1(torch, P, dev, steps=min(args.steps, 50), warmup=min(args.warmup, 5))
+        print(json.dumps({"metric": "solve time relative to the fully periodic solve at equal "
+                                    "FFT size S^3 (Figure 1)", "unit": "ratio",
+                          "data": "synthetic", "rows": rows}), flush=True)
         return
     P.load_library()
     n, bc, rho = workload_density(args.workload, H)

@@ -93,6 +93,24 @@ int poisson_plan_describe(int n1, int n2, int n3, unsigned bc_mask, int precisio
                           int axis_order[3], int S[3], size_t *workspace_bytes,
                           double *alg_bytes);
 
+/* A plan with a caller-chosen forward axis order (p, q, r), a permutation of
+ * 0, 1, 2 (NULL: the automatic order of poisson_plan).  For the axis-order
+ * study of Section 3: every order gives the same V up to rounding, but the
+ * number of 1D transforms, the bytes moved and so the time depend on it. */
+int poisson_plan_ordered(poisson_plan_t *out, int n1, int n2, int n3, unsigned bc_mask, double h,
+                         int precision, const int axis_order[3]);
+
+/* Host-only description as poisson_plan_describe, for a forced order
+ * (force_order NULL: automatic), plus the rows of the three forward steps
+ * (as poisson_plan_rows).  Any output pointer may be NULL. */
+int poisson_plan_describe_ordered(int n1, int n2, int n3, unsigned bc_mask, int precision,
+                                  const int force_order[3], int axis_order[3], int S[3],
+                                  size_t *workspace_bytes, double *alg_bytes, long long rows[3]);
+
+/* The same description of an existing plan (its actual axis order). */
+int poisson_plan_info(poisson_plan_t plan, int axis_order[3], int S[3], size_t *workspace_bytes,
+                      double *alg_bytes);
+
 /* Host-only: per forward step s = 0, 1, 2 of the customized 3D FFT in the
  * chosen order, the number of 1D transforms (rows) and their length, counted
  * as in Section 3 (complex rows: the second step has S_p * N_r rows).  The

@@ -33,8 +33,11 @@ from ._lib import (  # noqa: F401
     poisson_last_error,
     poisson_plan,
     poisson_plan_describe,
+    poisson_plan_describe_ordered,
     poisson_plan_destroy,
     poisson_plan_get_schedule,
+    poisson_plan_info,
+    poisson_plan_ordered,
     poisson_plan_rows,
     poisson_plan_set_schedule,
     poisson_plan_tune,
@@ -60,12 +63,13 @@ class Plan:
 
     rho and V are float32 device tensors of shape (n3, n2, n1) (x fastest)."""
 
-    def __init__(self, n, bc_mask, h, precision=POISSON_FP32, build_kernel=True, stream=None):
+    def __init__(self, n, bc_mask, h, precision=POISSON_FP32, build_kernel=True, stream=None,
+                 axis_order=None):
         self.n = tuple(int(v) for v in n)
         self.bc_mask = int(bc_mask)
         self.h = float(h)
-        self.info = poisson_plan_describe(*self.n, self.bc_mask, precision)
-        self.handle = poisson_plan(*self.n, self.bc_mask, self.h, precision)
+        self.handle = poisson_plan_ordered(*self.n, self.bc_mask, self.h, precision, axis_order)
+        self.info = poisson_plan_info(self.handle)
         if build_kernel:
             poisson_kernel_build(self.handle, stream)
 

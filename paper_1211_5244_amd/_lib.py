@@ -28,7 +28,8 @@ POISSON_FP32, POISSON_SPLIT_FP16, POISSON_SPLIT_BF16 = 0, 1, 2
 
 # every symbol include/poisson.h declares
 EXPORTED = (
-    "poisson_plan", "poisson_plan_describe", "poisson_plan_rows", "poisson_set_workspace",
+    "poisson_plan", "poisson_plan_ordered", "poisson_plan_describe",
+    "poisson_plan_describe_ordered", "poisson_plan_info", "poisson_plan_rows", "poisson_set_workspace",
     "poisson_kernel_set", "poisson_kernel_build", "poisson_kernel_get", "poisson_solve",
     "poisson_solve_passes",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
@@ -70,6 +71,12 @@ def load_library(path=None):
         "poisson_plan_describe": (_i, [_i, _i, _i, _u, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                        ctypes.POINTER(_sz), ctypes.POINTER(_d)]),
         "poisson_plan_rows": (_i, [_i, _i, _i, _u, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_i)]),
+        "poisson_plan_ordered": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _u, _d, _i, ctypes.POINTER(_i)]),
+        "poisson_plan_describe_ordered": (_i, [_i, _i, _i, _u, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
+                                               ctypes.POINTER(_i), ctypes.POINTER(_sz), ctypes.POINTER(_d),
+                                               ctypes.POINTER(ctypes.c_longlong)]),
+        "poisson_plan_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_sz),
+                                   ctypes.POINTER(_d)]),
         "poisson_set_workspace": (_i, [_vp, _vp, _sz]),
         "poisson_kernel_set": (_i, [_vp, _vp, _i]),
         "poisson_kernel_build": (_i, [_vp, _vp]),
@@ -131,6 +138,36 @@ def poisson_plan(n1, n2, n3, bc_mask, h, precision=POISSON_FP32):
     out = _vp()
     _check(load_library().poisson_plan(ctypes.byref(out), n1, n2, n3, bc_mask, h, precision))
     return out.value
+
+
+def poisson_plan_ordered(n1, n2, n3, bc_mask, h, precision=POISSON_FP32, axis_order=None):
+    out = _vp()
+    order = None if axis_order is None else (_i * 3)(*[int(a) for a in axis_order])
+    _check(load_library().poisson_plan_ordered(ctypes.byref(out), n1, n2, n3, bc_mask, h, precision,
+                                               order))
+    return out.value
+
+
+def poisson_plan_describe_ordered(n1, n2, n3, bc_mask, precision=POISSON_FP32, axis_order=None):
+    force = None if axis_order is None else (_i * 3)(*[int(a) for a in axis_order])
+    order = (_i * 3)()
+    S = (_i * 3)()
+    ws = _sz()
+    alg = _d()
+    rows = (ctypes.c_longlong * 3)()
+    _check(load_library().poisson_plan_describe_ordered(n1, n2, n3, bc_mask, precision, force, order, S,
+                                                        ctypes.byref(ws), ctypes.byref(alg), rows))
+    return dict(axis_order=tuple(order), S=tuple(S), workspace_bytes=ws.value, alg_bytes=alg.value,
+                rows=tuple(rows))
+
+
+def poisson_plan_info(plan):
+    order = (_i * 3)()
+    S = (_i * 3)()
+    ws = _sz()
+    alg = _d()
+    _check(load_library().poisson_plan_info(plan, order, S, ctypes.byref(ws), ctypes.byref(alg)))
+    return dict(axis_order=tuple(order), S=tuple(S), workspace_bytes=ws.value, alg_bytes=alg.value)
 
 
 def poisson_plan_describe(n1, n2, n3, bc_mask, precision=POISSON_FP32):

@@ -174,16 +174,27 @@ const char *poisson_last_error(void) { return g_last_error.c_str(); }
 int poisson_plan_describe(int n1, int n2, int n3, unsigned bc_mask, int precision,
                           int axis_order[3], int S[3], size_t *workspace_bytes,
                           double *alg_bytes) {
+  return poisson_plan_describe_ordered(n1, n2, n3, bc_mask, precision, nullptr, axis_order, S,
+                                       workspace_bytes, alg_bytes, nullptr);
+}
+
+int poisson_plan_describe_ordered(int n1, int n2, int n3, unsigned bc_mask, int precision,
+                                  const int force_order[3], int axis_order[3], int S[3],
+                                  size_t *workspace_bytes, double *alg_bytes, long long rows[3]) {
   try {
     Geometry g;
     std::string err;
-    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err);
+    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err, force_order);
     if (rc) return fail(rc, err);
     rc = check_precision(precision);
     if (rc) return rc;
+    const int p = g.order[0], q = g.order[1], r = g.order[2];
+    const long long R[3] = {(long long)g.n[q] * g.n[r], (long long)g.S[p] * g.n[r],
+                            (long long)g.S[p] * g.S[q]};
     for (int j = 0; j < 3; ++j) {
       if (axis_order) axis_order[j] = g.order[j];
       if (S) S[j] = g.S[j];
+      if (rows) rows[j] = R[j];
     }
     if (workspace_bytes) *workspace_bytes = g.ws_bytes;
     if (alg_bytes) *alg_bytes = g.alg_bytes;
@@ -216,13 +227,18 @@ int poisson_plan_rows(int n1, int n2, int n3, unsigned bc_mask, long long rows[3
 
 int poisson_plan(poisson_plan_t *out, int n1, int n2, int n3, unsigned bc_mask, double h,
                  int precision) {
+  return poisson_plan_ordered(out, n1, n2, n3, bc_mask, h, precision, nullptr);
+}
+
+int poisson_plan_ordered(poisson_plan_t *out, int n1, int n2, int n3, unsigned bc_mask, double h,
+                         int precision, const int axis_order[3]) {
   try {
     if (!out) return fail(POISSON_E_ARG, "out is NULL");
     *out = nullptr;
     if (!(h > 0.0) || !std::isfinite(h)) return fail(POISSON_E_ARG, "spacing h must be positive and finite");
     Geometry g;
     std::string err;
-    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err);
+    int rc = psn::build_geometry(n1, n2, n3, bc_mask, g, err, axis_order);
     if (rc) return fail(rc, err);
     rc = check_precision(precision);
     if (rc) return rc;
@@ -274,6 +290,18 @@ int poisson_plan(poisson_plan_t *out, int n1, int n2, int n3, unsigned bc_mask, 
   } catch (...) {
     return fail(POISSON_E_STATE, "unexpected exception");
   }
+}
+
+int poisson_plan_info(poisson_plan_t P, int axis_order[3], int S[3], size_t *workspace_bytes,
+                      double *alg_bytes) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  for (int j = 0; j < 3; ++j) {
+    if (axis_order) axis_order[j] = P->g.order[j];
+    if (S) S[j] = P->g.S[j];
+  }
+  if (workspace_bytes) *workspace_bytes = P->g.ws_bytes;
+  if (alg_bytes) *alg_bytes = P->g.alg_bytes;
+  return POISSON_OK;
 }
 
 int poisson_set_workspace(poisson_plan_t P, void *dev_ptr, size_t bytes) {

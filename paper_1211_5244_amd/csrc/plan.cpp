@@ -58,7 +58,8 @@ int third_axis(int a, int b) { return 3 - a - b; }
 
 }  // namespace
 
-int build_geometry(int n1, int n2, int n3, unsigned bc, Geometry &g, std::string &err) {
+int build_geometry(int n1, int n2, int n3, unsigned bc, Geometry &g, std::string &err,
+                   const int *force_order) {
   g = Geometry();
   const int n[3] = {n1, n2, n3};
   if (bc > 7u) {
@@ -99,6 +100,19 @@ int build_geometry(int n1, int n2, int n3, unsigned bc, Geometry &g, std::string
       best = k;
       best_bytes = b;
     }
+  }
+  if (force_order) {
+    // a caller-chosen order (the axis-order study of Section 3): any
+    // permutation of 0, 1, 2
+    const int *o = force_order;
+    if (o[0] < 0 || o[0] > 2 || o[1] < 0 || o[1] > 2 || o[2] < 0 || o[2] > 2 || o[0] == o[1] ||
+        o[0] == o[2] || o[1] == o[2]) {
+      err = "axis_order must be a permutation of 0, 1, 2";
+      return POISSON_E_ARG;
+    }
+    for (int k = 0; k < 6; ++k)
+      if (perms[k][0] == o[0] && perms[k][1] == o[1] && perms[k][2] == o[2]) best = k;
+    best_bytes = algorithmic_bytes(g.n, g.S, perms[best]);
   }
   const int p = perms[best][0], q = perms[best][1], r = perms[best][2];
   g.order[0] = p;

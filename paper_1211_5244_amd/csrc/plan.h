@@ -48,9 +48,11 @@ struct Geometry {
   Pass pass[5];
 };
 
-// Fills g for the given problem.  Returns 0 or a negative POISSON_E_* code
-// with a message in err.
-int build_geometry(int n1, int n2, int n3, unsigned bc, Geometry &g, std::string &err);
+// Fills g for the given problem, with the minimum-byte axis order or, if
+// force_order is not null, that forward order (p, q, r).  Returns 0 or a
+// negative POISSON_E_* code with a message in err.
+int build_geometry(int n1, int n2, int n3, unsigned bc, Geometry &g, std::string &err,
+                   const int *force_order = nullptr);
 
 // Minimum HBM bytes of one solve for axis order (p, q, r) (five passes, each
 // reading and writing its data once, plus the float32 K^F octant).

@@ -3,6 +3,7 @@ the header declares, and its planner follows the paper's row counts
 (Section 3) and the byte model of the five-pass schedule.  No device calls."""
 
 import ctypes
+import itertools
 import json
 import os
 import re
@@ -78,6 +79,51 @@ def test_fft_work_ratios_of_the_paper():
     # surface with free y last vs the periodic problem of the same FFT size
     per = _work((N, S, N), 0)
     assert Fraction(_work((N, N, N), 2), per) == Fraction(*g["surface_free_axis_last_vs_periodic"])
+
+
+def _work_ordered(n, bc, order):
+    d = P.poisson_plan_describe_ordered(*n, bc, axis_order=order)
+    lens = [d["S"][a] for a in d["axis_order"]]
+    return sum(r * l for r, l in zip(d["rows"], lens))
+
+
+@pytest.mark.parametrize("bc", range(8))
+def test_forced_orders_and_the_automatic_choice(bc):
+    n = (48, 32, 24)
+    auto = P.poisson_plan_describe(*n, bc)
+    best = None
+    for order in itertools.permutations(range(3)):
+        d = P.poisson_plan_describe_ordered(*n, bc, axis_order=order)
+        assert d["axis_order"] == order
+        assert d["S"] == auto["S"]
+        # rows of Section 3 in this order: N_q N_r, S_p N_r, S_p S_q
+        p, q, r = order
+        assert d["rows"] == (n[q] * n[r], d["S"][p] * n[r], d["S"][p] * d["S"][q])
+        best = d["alg_bytes"] if best is None else min(best, d["alg_bytes"])
+    assert auto["alg_bytes"] == best
+    assert P.poisson_plan_describe_ordered(*n, bc)["axis_order"] == auto["axis_order"]
+
+
+def test_axis_order_ablation_ratios():
+    """Section 3's row rule in the orders it compares.  Wire (x, y free, z
+    periodic, N^3 data): z first costs N^3 + 2N^3 + 4N^3 of the full 12N^3
+    (7/12, as free); z last 2N^3 + 4N^3 + 4N^3 (5/6).  Surface (y free):
+    y last costs 4N^3 of 6N^3 (2/3); y first 6N^3 (no gain)."""
+    N = 64
+    S = 2 * N
+    wire_full = 3 * S * S * N          # full padded 3D transform of (2N, 2N, N)
+    assert Fraction(_work_ordered((N, N, N), 3, (2, 0, 1)), wire_full) == Fraction(7, 12)
+    assert Fraction(_work_ordered((N, N, N), 3, (0, 1, 2)), wire_full) == Fraction(5, 6)
+    surf_full = 3 * N * S * N          # (N, 2N, N), y free
+    assert Fraction(_work_ordered((N, N, N), 2, (0, 2, 1)), surf_full) == Fraction(2, 3)
+    assert Fraction(_work_ordered((N, N, N), 2, (1, 0, 2)), surf_full) == Fraction(1, 1)
+
+
+@pytest.mark.parametrize("order", [(0, 0, 1), (0, 1, 3), (-1, 1, 2), (2, 2, 2)])
+def test_forced_order_must_be_a_permutation(order):
+    with pytest.raises(P.PoissonError) as e:
+        P.poisson_plan_describe_ordered(16, 16, 16, 7, axis_order=order)
+    assert e.value.code == P._lib.POISSON_E_ARG
 
 
 def test_transfer_fractions_of_the_paper():

@@ -104,6 +104,21 @@ def test_solve_parity_mixed_radix(torch_dev, n, bc):
     _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"{n} bc={bc}")
 
 
+@pytest.mark.parametrize("bc", [7, 3, 2, 5, 0])
+def test_every_axis_order_matches_oracle(torch_dev, bc):
+    """Forced forward axis orders (Section 3's axis-order study) change the
+    passes' layouts and row counts, not V."""
+    import itertools
+    n = (24, 32, 48) if bc else (24, 32, 12)
+    rho = _density(n, bc, seed=300 + bc)
+    ref = oracle.solve(rho.astype(np.float64), bc, H)
+    for order in itertools.permutations(range(3)):
+        plan = P.Plan(n, bc, H, axis_order=order)
+        assert tuple(plan.info["axis_order"]) == order
+        V, _ = _gpu_solve(torch_dev, n, bc, rho, plan=plan)
+        _check(V, ref, f"{n} bc={bc} order={order}")
+
+
 def test_kernel_set_from_oracle_octant(torch_dev):
     """poisson_kernel_set with the oracle's octant gives the same solve."""
     n, bc = (32, 24, 48), 3
