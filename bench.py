@@ -167,6 +167,38 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     return out
 
 
+def bench_host(torch, P, plan, r, count=20):
+    """Transfer-inclusive rates (Sections 1 and 4 count the copies of rho to
+    the device and of V back): one solve at a time through pinned host
+    buffers (upload, solve, download, no overlap), and the pipeline that
+    overlaps the copies of neighbouring solves with the current solve."""
+    stream = torch.cuda.current_stream(r.device)
+    rho_h = [r.cpu().pin_memory() for _ in range(2)]
+    V_h = [torch.empty_like(rho_h[0]).pin_memory() for _ in range(2)]
+    P.poisson_solve_host(plan.handle, rho_h[0], V_h[0], stream)  # first call allocates
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(count):
+        P.poisson_solve_host(plan.handle, rho_h[i & 1], V_h[i & 1], stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_one = e0.elapsed_time(e1) / count
+    rl = [rho_h[i & 1] for i in range(count)]
+    vl = [V_h[i & 1] for i in range(count)]
+    e0.record(stream)
+    P.poisson_solve_host_many(plan.handle, rl, vl, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_pipe = e0.elapsed_time(e1) / count
+    nbytes = 2 * r.numel() * 4
+    return {"bytes_per_solve": nbytes,
+            "one_at_a_time": {"ms": t_one, "solves_per_s": 1000.0 / t_one,
+                              "pcie_gbs": nbytes / (t_one * 1e-3) / 1e9},
+            "pipelined": {"ms": t_pipe, "solves_per_s": 1000.0 / t_pipe,
+                          "pcie_gbs": nbytes / (t_pipe * 1e-3) / 1e9, "solves": count}}
+
+
 def fig1(torch, P, dev, steps, warmup):
     """Figure 1's experiment (Section 4): time of each BC class relative to the
     fully periodic solve of the same FFT size S^3, with Section 3's axis-order
@@ -338,6 +370,7 @@ def main():
         "step_ms_percentiles": step_pct,  # per solve, from the per-pass event loop
         "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
     }
+    out["host_transfer"] = bench_host(torch, P, plan, r)
     # split-precision modes on the same workload: time and accuracy
     if not args.no_split:
         out["split"] = {}

@@ -162,6 +162,22 @@ int poisson_solve(poisson_plan_t plan, const float *rho_dev, float *V_dev, void 
 int poisson_solve_passes(poisson_plan_t plan, const float *rho_dev, float *V_dev, int first,
                          int last, void *stream);
 
+/* Solves on host buffers (Sections 1 and 4 count the transfers of the
+ * density to the device and of the potential back).  poisson_solve_host
+ * copies rho_host to a device grid of the plan, solves in place and copies
+ * V back, all ordered on `stream`; poisson_solve_host_many does this for
+ * `count` densities through two device grids and two copy streams of the
+ * plan, so the upload of density i+1 and the download of potential i-1
+ * overlap the solve of density i.  rho_host[i] == V_host[i] is allowed.
+ * Host buffers should be pinned (hipHostMalloc) for the copies to run
+ * asynchronously and overlap.  Asynchronous: the caller's stream completes
+ * after the last copy to the host.  The first call allocates the two grids
+ * and creates the copy streams (default priority); later calls allocate
+ * nothing.  Not graph-capturable (it uses the plan's own streams). */
+int poisson_solve_host(poisson_plan_t plan, const float *rho_host, float *V_host, void *stream);
+int poisson_solve_host_many(poisson_plan_t plan, int count, const float *const *rho_host,
+                            float *const *V_host, void *stream);
+
 /* Release the plan and every device buffer it owns (not a caller workspace).
  * Waits for the device to finish work that may use them. */
 int poisson_plan_destroy(poisson_plan_t plan);

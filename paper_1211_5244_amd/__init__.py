@@ -44,6 +44,8 @@ from ._lib import (  # noqa: F401
     poisson_rel_l2,
     poisson_set_workspace,
     poisson_solve,
+    poisson_solve_host,
+    poisson_solve_host_many,
     poisson_solve_passes,
 )
 
@@ -93,6 +95,20 @@ class Plan:
             stream = torch.cuda.current_stream(rho.device)
         poisson_solve(self.handle, rho, V, stream)
         return V
+
+    def solve_host(self, rho_list, V_list, stream=None):
+        """Solves on pinned host tensors of shape (n3, n2, n1): uploads,
+        solves and downloads with the copies overlapping the solves."""
+        import torch
+        for i, (r, v) in enumerate(zip(rho_list, V_list)):
+            for t, what in ((r, f"rho[{i}]"), (v, f"V[{i}]")):
+                if t.device.type != "cpu" or t.dtype != torch.float32 or not t.is_contiguous():
+                    raise TypeError(f"{what} must be a contiguous float32 host tensor")
+                if tuple(t.shape) != (self.n[2], self.n[1], self.n[0]):
+                    raise ValueError(f"{what} has shape {tuple(t.shape)}")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        poisson_solve_host_many(self.handle, rho_list, V_list, stream)
 
     @property
     def schedule(self):

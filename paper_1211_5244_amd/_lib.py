@@ -31,7 +31,7 @@ EXPORTED = (
     "poisson_plan", "poisson_plan_ordered", "poisson_plan_describe",
     "poisson_plan_describe_ordered", "poisson_plan_info", "poisson_plan_rows", "poisson_set_workspace",
     "poisson_kernel_set", "poisson_kernel_build", "poisson_kernel_get", "poisson_solve",
-    "poisson_solve_passes",
+    "poisson_solve_passes", "poisson_solve_host", "poisson_solve_host_many",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
     "poisson_plan_get_schedule", "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2",
@@ -83,6 +83,8 @@ def load_library(path=None):
         "poisson_kernel_get": (_i, [_vp, _vp]),
         "poisson_solve": (_i, [_vp, _vp, _vp, _vp]),
         "poisson_solve_passes": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
+        "poisson_solve_host": (_i, [_vp, _vp, _vp, _vp]),
+        "poisson_solve_host_many": (_i, [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
         "poisson_plan_destroy": (_i, [_vp]),
         "poisson_batch_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), ctypes.POINTER(_u),
                                       ctypes.POINTER(_d), _i]),
@@ -217,6 +219,18 @@ def poisson_solve(plan, rho, V, stream=None):
 
 def poisson_solve_passes(plan, rho, V, first, last, stream=None):
     _check(load_library().poisson_solve_passes(plan, _ptr(rho), _ptr(V), first, last, _stream(stream)))
+
+
+def poisson_solve_host(plan, rho_host, V_host, stream=None):
+    """rho_host / V_host: host addresses (pinned torch CPU tensors or ints)."""
+    _check(load_library().poisson_solve_host(plan, _ptr(rho_host), _ptr(V_host), _stream(stream)))
+
+
+def poisson_solve_host_many(plan, rho_list, V_list, stream=None):
+    count = len(rho_list)
+    r = (_vp * count)(*[_ptr(x) for x in rho_list])
+    v = (_vp * count)(*[_ptr(x) for x in V_list])
+    _check(load_library().poisson_solve_host_many(plan, count, r, v, _stream(stream)))
 
 
 def poisson_plan_destroy(plan):

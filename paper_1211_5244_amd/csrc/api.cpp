@@ -71,6 +71,13 @@ struct poisson_plan_s {
   bool own_ws = false;
   bool auto_ws = true;  // allocate a workspace when the kernel is set
   bool kernel_ready = false;
+  // host-buffer solves: two device grids and two copy streams (created on
+  // first use, default priority)
+  float *io[2] = {nullptr, nullptr};
+  hipStream_t h2d = nullptr, d2h = nullptr;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_solved[2] = {nullptr, nullptr},
+             ev_out[2] = {nullptr, nullptr};
 };
 
 struct poisson_batch_s {
@@ -108,6 +115,30 @@ int plan_alloc(poisson_plan_t P, void **ptr, size_t bytes, const char *what) {
 void plan_free_all(poisson_plan_t P) {
   for (void *p : P->owned) (void)hipFree(p);
   P->owned.clear();
+  for (hipEvent_t *e : {&P->ev_start, &P->ev_end, &P->ev_in[0], &P->ev_in[1], &P->ev_solved[0],
+                        &P->ev_solved[1], &P->ev_out[0], &P->ev_out[1]})
+    if (*e) (void)hipEventDestroy(*e), *e = nullptr;
+  if (P->h2d) (void)hipStreamDestroy(P->h2d), P->h2d = nullptr;
+  if (P->d2h) (void)hipStreamDestroy(P->d2h), P->d2h = nullptr;
+}
+
+// Device grids, copy streams and events of the host-buffer solves.
+int ensure_host_io(poisson_plan_t P) {
+  if (P->io[1]) return POISSON_OK;
+  const size_t bytes = sizeof(float) * size_t(P->g.n[0]) * P->g.n[1] * P->g.n[2];
+  for (int b = 0; b < 2; ++b) {
+    if (P->io[b]) continue;
+    void *p = nullptr;
+    int rc = plan_alloc(P, &p, bytes, "hipMalloc(host-solve grid)");
+    if (rc) return rc;
+    P->io[b] = static_cast<float *>(p);
+  }
+  if (!P->h2d) PSN_TRY_HIP(hipStreamCreateWithFlags(&P->h2d, hipStreamNonBlocking), "hipStreamCreate");
+  if (!P->d2h) PSN_TRY_HIP(hipStreamCreateWithFlags(&P->d2h, hipStreamNonBlocking), "hipStreamCreate");
+  for (hipEvent_t *e : {&P->ev_start, &P->ev_end, &P->ev_in[0], &P->ev_in[1], &P->ev_solved[0],
+                        &P->ev_solved[1], &P->ev_out[0], &P->ev_out[1]})
+    if (!*e) PSN_TRY_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+  return POISSON_OK;
 }
 
 int ensure_workspace(poisson_plan_t P) {
@@ -426,6 +457,53 @@ int poisson_solve_passes(poisson_plan_t P, const float *rho, float *V, int first
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
   return enqueue_passes(P, 1, &rho, &V, P->ws, first, last, s);
+}
+
+int poisson_solve_host(poisson_plan_t P, const float *rho_host, float *V_host, void *stream) {
+  return poisson_solve_host_many(P, 1, &rho_host, &V_host, stream);
+}
+
+int poisson_solve_host_many(poisson_plan_t P, int count, const float *const *rho_host,
+                            float *const *V_host, void *stream) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  if (count < 1 || !rho_host || !V_host) return fail(POISSON_E_ARG, "empty request or NULL array");
+  for (int i = 0; i < count; ++i)
+    if (!rho_host[i] || !V_host[i]) return fail(POISSON_E_ARG, "host pointer " + std::to_string(i) + " is NULL");
+  if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "no K^F has been set or built");
+  if (!P->ws) return fail(POISSON_E_STATE, "no workspace");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  int rc = ensure_host_io(P);
+  if (rc) return rc;
+  hipStream_t cs = static_cast<hipStream_t>(stream);
+  const size_t bytes = sizeof(float) * size_t(P->g.n[0]) * P->g.n[1] * P->g.n[2];
+  // the copy streams start after the caller's earlier work (including an
+  // earlier call's last copies, which the caller's stream waited for)
+  PSN_TRY_HIP(hipEventRecord(P->ev_start, cs), "hipEventRecord");
+  PSN_TRY_HIP(hipStreamWaitEvent(P->h2d, P->ev_start, 0), "hipStreamWaitEvent");
+  PSN_TRY_HIP(hipStreamWaitEvent(P->d2h, P->ev_start, 0), "hipStreamWaitEvent");
+  for (int i = 0; i < count; ++i) {
+    const int b = i & 1;
+    float *buf = P->io[b];
+    // buffer b is free once its previous result has left the device
+    if (i >= 2) PSN_TRY_HIP(hipStreamWaitEvent(P->h2d, P->ev_out[b], 0), "hipStreamWaitEvent");
+    PSN_TRY_HIP(hipMemcpyAsync(buf, rho_host[i], bytes, hipMemcpyHostToDevice, P->h2d),
+                "hipMemcpyAsync(density to device)");
+    PSN_TRY_HIP(hipEventRecord(P->ev_in[b], P->h2d), "hipEventRecord");
+    PSN_TRY_HIP(hipStreamWaitEvent(cs, P->ev_in[b], 0), "hipStreamWaitEvent");
+    const float *r = buf;
+    rc = enqueue_passes(P, 1, &r, &buf, P->ws, 0, 4, cs);
+    if (rc) return rc;
+    PSN_TRY_HIP(hipEventRecord(P->ev_solved[b], cs), "hipEventRecord");
+    PSN_TRY_HIP(hipStreamWaitEvent(P->d2h, P->ev_solved[b], 0), "hipStreamWaitEvent");
+    PSN_TRY_HIP(hipMemcpyAsync(V_host[i], buf, bytes, hipMemcpyDeviceToHost, P->d2h),
+                "hipMemcpyAsync(potential to host)");
+    PSN_TRY_HIP(hipEventRecord(P->ev_out[b], P->d2h), "hipEventRecord");
+  }
+  // the caller's stream completes after the last copy to the host
+  PSN_TRY_HIP(hipEventRecord(P->ev_end, P->d2h), "hipEventRecord");
+  PSN_TRY_HIP(hipStreamWaitEvent(cs, P->ev_end, 0), "hipStreamWaitEvent");
+  return POISSON_OK;
 }
 
 int poisson_plan_destroy(poisson_plan_t P) {
