@@ -186,7 +186,7 @@ int poisson_plan_destroy(poisson_plan_t plan);
  * (Section 5 motivates many densities per run).  n holds 3*count sizes,
  * bc_mask and h one entry per solve.  Solves with equal (n, bc_mask, h)
  * share one plan and one K^F.  The batch owns one workspace: each plan's
- * solves run in chunks of up to 64 whose intermediates fit a budget (96 MiB
+ * solves run in chunks of up to 64 whose intermediates fit a budget (384 MiB
  * by default, or the environment variable POISSON_BATCH_CHUNK_MB read at
  * creation), and every pass of a chunk is one kernel launch. */
 int poisson_batch_create(poisson_batch_t *out, int count, const int *n,
@@ -202,37 +202,45 @@ int poisson_batch_destroy(poisson_batch_t batch);
 
 /* Schedules and the autotuner.
  *
- * The radix decomposition of each FFT length is fixed.  Passes 0, 1, 3 and 4
- * stage their lines through LDS in tiles of W consecutive lines; the tile
- * schedule tile_sel = 0..3 asks for W of about 16, 8, 4 or 32 complex lines
- * (0 is the default).  A schedule changes which lines a workgroup transforms
- * together and how long its HBM row segments are, never a line's
- * arithmetic: results are bitwise identical under every schedule.  Float32
- * mode compiles every schedule that fits the LDS of a compute unit and is
- * distinct from a lower one; split modes compile schedule 0 only.  Pass 2
- * (the fused convolution) has no tile schedule (always 0). */
+ * The radix decomposition of each FFT length is fixed.  Each pass has a
+ * schedule 0..7 (0 is the default):
+ *  - bits 0-1, tile width: passes 0, 1, 3 and 4 stage their lines through
+ *    LDS in tiles of W consecutive lines, W about 16, 8, 4 or 32 complex
+ *    lines for values 0..3.  Float32 mode compiles every width that fits
+ *    the LDS of a compute unit and differs from a lower one; split modes
+ *    compile width 0 only; pass 2 (the fused convolution) has no tile and
+ *    takes width 0 only.
+ *  - bit 2, workgroup order: 1 gives each of the chip's 8 XCDs (each with
+ *    its own L2) a contiguous run of tiles (or kernel rows) per round
+ *    instead of every eighth one.
+ * A schedule changes which lines a workgroup transforms together, where it
+ * runs and how long its HBM row segments are, never a line's arithmetic:
+ * results are bitwise identical under every schedule. */
 
-/* Set the five passes' tile schedules.  POISSON_E_UNSUPPORTED if one is not
- * compiled for its pass (then nothing changes). */
+/* Set the five passes' schedules.  POISSON_E_ARG if one is outside 0..7,
+ * POISSON_E_UNSUPPORTED if its tile width is not compiled for its pass
+ * (then nothing changes). */
 int poisson_plan_set_schedule(poisson_plan_t plan, const int tile_sel[5]);
 
 /* Current schedules and, per pass, the complex lines per tile they give
  * (0 for pass 2).  Either pointer may be NULL. */
 int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lines[5]);
 
-/* Autotuner: times every compiled tile schedule of every pass on this
- * device (reps launches per candidate after a warm-up, best of two rounds,
- * hipEvents on `stream`) and keeps the fastest; a candidate replaces the
- * current choice only if at least 1% faster.  Runs solves on rho_dev and
- * V_dev: V_dev (and the workspace) receive scratch values.  pass_ms (may
- * be NULL) receives the chosen schedule's time per pass.  reps <= 0 means
- * 10.  Needs K^F and a workspace; synchronous. */
+/* Autotuner: coordinate descent over the five passes.  For each pass, every
+ * compiled schedule is timed as whole solves on this device (reps solves
+ * per candidate after a warm-up, best of two rounds, hipEvents on `stream`),
+ * so a candidate is charged for what it leaves in the caches for the next
+ * pass; it replaces the current choice only if the solve gets at least 1%
+ * faster.  Runs solves on rho_dev and V_dev: V_dev (and the workspace)
+ * receive scratch values.  pass_ms (may be NULL) receives the chosen
+ * schedule's per-pass times.  reps <= 0 means 10.  Needs K^F and a
+ * workspace; synchronous. */
 int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, int reps,
                       double pass_ms[5], void *stream);
 
 /* Autotuner for a batch: tunes each distinct plan's tile schedules on its
  * first chunk, then times whole batch solves for intermediates budgets of
- * 32..256 MiB and keeps the fastest (chunk_mb, may be NULL, receives it).
+ * 32..512 MiB and keeps the fastest (chunk_mb, may be NULL, receives it).
  * The arrays are those of poisson_batch_solve; V receives scratch values.
  * May reallocate the batch workspace (graphs captured before then must be
  * captured again).  reps <= 0 means 5.  Synchronous. */

@@ -38,8 +38,9 @@ EXPORTED = (
     "poisson_last_error",
 )
 
-# tile schedules per pass (poisson_plan_set_schedule)
-TILE_SCHEDULES = 4
+# schedules per pass (poisson_plan_set_schedule): tile width in bits 0-1,
+# XCD-blocked workgroup order in bit 2
+TILE_SCHEDULES = 8
 
 
 class PoissonError(RuntimeError):

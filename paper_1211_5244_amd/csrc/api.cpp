@@ -85,7 +85,7 @@ struct poisson_batch_s {
   std::vector<int> which;                   // solve i uses plans[which[i]]
   std::vector<std::vector<int>> members;    // per plan: its solves, in order
   std::vector<int> chunk;                   // per plan: solves per launch
-  double chunk_mb = 96.0;                   // intermediates budget of one launch
+  double chunk_mb = 384.0;                  // intermediates budget of one launch
   void *ws = nullptr;                       // shared by all chunks (one stream)
   size_t ws_bytes = 0;
   int device = 0;
@@ -187,6 +187,14 @@ size_t batch_chunks(poisson_batch_t B, double budget_mb, std::vector<int> &chunk
   }
   B->chunk_mb = budget_mb;
   return ws;
+}
+
+// Whether schedule `sched` (tile width in bits 0-1, XCD order in bit 2) is
+// compiled for pass k of plan P.  The conv pass has no tile width.
+bool schedule_valid(poisson_plan_t P, int k, int sched) {
+  if (sched < 0 || sched >= psn::kSchedules) return false;
+  if (k == psn::KIND_CONV) return (sched & 3) == 0;
+  return psn::pass_tile_lines(P->g.pass[k], sched, P->precision) > 0;
 }
 
 int finish_kernel(poisson_plan_t P, hipStream_t s) {
@@ -561,10 +569,11 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n, const un
       B->members[it->second].push_back(i);
     }
     // Solves per launch: as many as keep a chunk's intermediates within the
-    // budget (default 96 MiB, below the 256 MB Infinity Cache, so the five
-    // passes of a chunk re-read their intermediates from cache), at most
-    // kMaxBatch.  poisson_batch_tune may pick another budget.
-    double budget_mb = 96.0;
+    // budget, at most kMaxBatch.  Larger chunks mean fewer, fuller launches;
+    // on the 512-solve mixed batch 384 MiB measured fastest (96 MiB, which
+    // would keep a chunk in the 256 MB last-level cache, was 17% slower).
+    // poisson_batch_tune picks the budget on the device.
+    double budget_mb = 384.0;
     if (const char *env = std::getenv("POISSON_BATCH_CHUNK_MB")) {
       const double v = std::atof(env);
       if (v > 0) budget_mb = v;
@@ -637,12 +646,11 @@ int poisson_batch_destroy(poisson_batch_t B) {
 int poisson_plan_set_schedule(poisson_plan_t P, const int tile_sel[5]) {
   if (!P || !tile_sel) return fail(POISSON_E_ARG, "NULL argument");
   for (int k = 0; k < 5; ++k) {
-    if (tile_sel[k] < 0 || tile_sel[k] >= psn::kTileSchedules)
-      return fail(POISSON_E_ARG, "tile schedule out of range");
-    if (k == psn::KIND_CONV ? tile_sel[k] != 0
-                            : psn::pass_tile_lines(P->g.pass[k], tile_sel[k], P->precision) == 0)
+    if (tile_sel[k] < 0 || tile_sel[k] >= psn::kSchedules)
+      return fail(POISSON_E_ARG, "schedule out of range");
+    if (!schedule_valid(P, k, tile_sel[k]))
       return fail(POISSON_E_UNSUPPORTED,
-                  "tile schedule " + std::to_string(tile_sel[k]) + " is not compiled for pass " +
+                  "schedule " + std::to_string(tile_sel[k]) + " is not compiled for pass " +
                       std::to_string(k) + " of this plan");
   }
   for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = tile_sel[k];
@@ -692,36 +700,67 @@ template <typename F> int time_enqueue(F &&enqueue, hipStream_t s, int reps, dou
   return rc;
 }
 
-// Picks each pass's fastest tile schedule for `count` solves of plan P run
-// together (arrays rho/V, intermediates in ws).  A schedule replaces the
-// current choice only when it is at least 1% faster.
+// Picks each pass's schedule for `count` solves of plan P run together
+// (arrays rho/V, intermediates in ws) by coordinate descent over the passes:
+// a candidate is timed as whole solves, so that what one pass leaves in the
+// caches (or evicts) for the next is part of its cost; it replaces the
+// current choice only when the solve gets at least 1% faster.  pass_ms (may
+// be null) receives the final schedule's per-pass times, from events between
+// the passes of whole solves.
 int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float *const *V,
                      void *ws, hipStream_t s, int reps, double *pass_ms) {
-  int rc = enqueue_passes(P, count, rho, V, ws, 0, 4, s);  // every pass reads written data
+  auto solve = [&] { return enqueue_passes(P, count, rho, V, ws, 0, 4, s); };
+  double best = 0;
+  int rc = time_enqueue(solve, s, reps, &best);
   if (rc) return rc;
   for (int k = 0; k < 5; ++k) {
     psn::Pass &pass = P->g.pass[k];
     const int keep = pass.tile_sel;
-    int best_ts = -1;
-    double best = INFINITY;
-    for (int ts = 0; ts < psn::kTileSchedules; ++ts) {
-      if (k == psn::KIND_CONV ? ts != 0 : psn::pass_tile_lines(pass, ts, P->precision) == 0) continue;
-      pass.tile_sel = ts;
+    int best_sel = keep;
+    for (int sel = 0; sel < psn::kSchedules; ++sel) {
+      if (sel == keep || !schedule_valid(P, k, sel)) continue;
+      pass.tile_sel = sel;
       double t = 0;
-      rc = time_enqueue([&] { return enqueue_passes(P, count, rho, V, ws, k, k, s); }, s, reps, &t);
+      rc = time_enqueue(solve, s, reps, &t);
       if (rc) {
         pass.tile_sel = keep;
         return rc;
       }
-      if (best_ts < 0 || t < 0.99 * best) {
+      if (t < 0.99 * best) {
         best = t;
-        best_ts = ts;
+        best_sel = sel;
       }
     }
-    pass.tile_sel = best_ts < 0 ? 0 : best_ts;
-    if (pass_ms) pass_ms[k] = best;
+    pass.tile_sel = best_sel;
   }
-  return POISSON_OK;
+  if (!pass_ms) return POISSON_OK;
+  hipEvent_t ev[6] = {};
+  for (auto &e : ev) {
+    hipError_t he = hipEventCreate(&e);
+    if (he != hipSuccess) {
+      for (auto &f : ev)
+        if (f) (void)hipEventDestroy(f);
+      return hip_fail(he, "hipEventCreate");
+    }
+  }
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < reps && rc == POISSON_OK; ++r) {
+    hipError_t he = hipEventRecord(ev[0], s);
+    for (int k = 0; k < 5 && he == hipSuccess && rc == POISSON_OK; ++k) {
+      rc = enqueue_passes(P, count, rho, V, ws, k, k, s);
+      if (rc == POISSON_OK) he = hipEventRecord(ev[k + 1], s);
+    }
+    if (he == hipSuccess) he = hipEventSynchronize(ev[5]);
+    for (int k = 0; k < 5 && he == hipSuccess; ++k) {
+      float t = 0.f;
+      he = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      acc[k] += t;
+    }
+    if (he != hipSuccess && rc == POISSON_OK) rc = hip_fail(he, "timing events");
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < 5; ++k) pass_ms[k] = acc[k] / reps;
+  return rc;
 }
 
 }  // namespace
@@ -766,7 +805,7 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
   }
   // 2. the intermediates budget of one launch, timed on the whole batch
   std::vector<double> budgets = {B->chunk_mb};  // the current budget first
-  for (double mb : {32.0, 64.0, 96.0, 128.0, 192.0, 256.0})
+  for (double mb : {32.0, 64.0, 96.0, 128.0, 192.0, 256.0, 384.0, 512.0})
     if (mb != B->chunk_mb) budgets.push_back(mb);
   double best_mb = B->chunk_mb, best = INFINITY;
   {

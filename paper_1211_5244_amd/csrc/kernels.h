@@ -29,12 +29,14 @@ struct PassIO {
 hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const float *kf,
                        int S_q, int mode, hipStream_t stream);
 
-// Tile schedules of the tiled passes (P.tile_sel = 0..kTileSchedules-1).
-// Complex lines per workgroup tile that schedule ts gives pass P in `mode`,
-// or 0 where that schedule is not compiled (it then runs as schedule 0).
-// The conv pass has no tile schedule (always 0).
+// Pass schedules (P.tile_sel = 0..kSchedules-1): bits 0-1 select the tile
+// width of a tiled pass (kTileSchedules choices; the conv pass has none),
+// bit 2 the XCD-blocked workgroup order.  pass_tile_lines gives the complex
+// lines per workgroup tile of schedule `sched` for pass P in `mode`, or 0
+// where its tile width is not compiled (it then runs as width 0).
 constexpr int kTileSchedules = 4;
-int pass_tile_lines(const Pass &P, int ts, int mode);
+constexpr int kSchedules = 8;
+int pass_tile_lines(const Pass &P, int sched, int mode);
 
 // float64 K^F octant of the default Green's function (layout of the C ABI:
 // k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.

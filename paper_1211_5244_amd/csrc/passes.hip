@@ -135,6 +135,7 @@ struct PassParams {
   int tiles_per_batch;
   int tiles_per_solve;
   int ntiles;
+  int xcd;  // 1: XCD-blocked tile order (block_order)
 };
 
 
@@ -182,6 +183,17 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p) {
   return make_float2(v.x, v.y);
 }
 __device__ __forceinline__ float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip
+// (workgroup b runs on XCD b % 8, each XCD with its own L2).  With `xcd` set
+// (grid a multiple of 8), workgroup b takes the virtual index that gives
+// each XCD a contiguous run of tiles per round: XCD x's j-th workgroup gets
+// x * (G / 8) + j, so neighbouring tiles, which read neighbouring row
+// segments, share an L2 and stream whole DRAM rows.
+__device__ __forceinline__ int block_order(int xcd) {
+  const int b = blockIdx.x, G = gridDim.x;
+  return xcd ? (b & 7) * (G >> 3) + (b >> 3) : b;
+}
 
 // A ROWS x W tile moved between HBM (rows at stride `sl`, W consecutive
 // elements per row) and LDS (row stride LD) by all NT threads, through
@@ -265,7 +277,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
     }
   };
 
-  int tile = blockIdx.x;
+  int tile = block_order(a.xcd);
   if (tile < a.ntiles) fetch(tile);
   while (tile < a.ntiles) {
     const TileCoord q = tile_coord(a, tile, W);
@@ -349,7 +361,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
     }
   };
 
-  int tile = blockIdx.x;
+  int tile = block_order(a.xcd);
   if (tile < a.ntiles) fetch(tile);
   while (tile < a.ntiles) {
     const TileCoord q = tile_coord(a, tile, W);
@@ -428,7 +440,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
   eng.init(a.tw, lane);
 
   TileRegs<ROWS_IN, W, NT, LDC, float2> pf;
-  int tile = blockIdx.x;
+  int tile = block_order(a.xcd);
   if (tile < a.ntiles) {
     const TileCoord q = tile_coord(a, tile, W);
     pf.load(static_cast<const float2 *>(a.in[q.solve]) + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
@@ -502,6 +514,7 @@ struct ConvParams {
   int H;              // number of k_p planes
   int nrows;          // H * kq_half kernel rows per solve
   int nsolve;
+  int xcd;            // 1: XCD-blocked workgroup order (block_order)
 };
 
 constexpr int kConvWaves = 4;
@@ -524,7 +537,7 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
   float2 *xch = smem + (wave * LPW + g) * SLOTS;
   float2 *wave_lines = smem + wave * LPW * SLOTS;
 
-  const int row0 = (blockIdx.x * kConvWaves + wave) * LPW + g;
+  const int row0 = (block_order(a.xcd) * kConvWaves + wave) * LPW + g;
   if (!__any(row0 < a.nrows * a.nsolve)) return;  // whole wavefront idle
 
   LineEngine<L, MODE> eng;
@@ -638,6 +651,7 @@ PassParams make_params(const Pass &P, const PassIO &io, const float2 *tw, int W)
   a.tiles_per_batch = (P.ext_tile + W - 1) / W;
   a.tiles_per_solve = a.tiles_per_batch * P.ext_batch;
   a.ntiles = a.tiles_per_solve * io.count;
+  a.xcd = 0;
   return a;
 }
 
@@ -659,6 +673,7 @@ hipError_t launch_c2c_ts(const Pass &P, const PassIO &io, const float2 *tw, hipS
   auto k = c2c_kernel<L, INV, IT, OT, PC, MODE, TS>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
+  a.xcd = ((P.tile_sel >> 2) & 1) && grid % 8 == 0;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
@@ -670,6 +685,7 @@ hipError_t launch_r2c_ts(const Pass &P, const PassIO &io, const float2 *tw, hipS
   auto k = r2c_kernel<L, IT, PAD, MODE, TS>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
+  a.xcd = ((P.tile_sel >> 2) & 1) && grid % 8 == 0;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
@@ -681,6 +697,7 @@ hipError_t launch_c2r_ts(const Pass &P, const PassIO &io, const float2 *tw, hipS
   auto k = c2r_kernel<L, OT, CROP, MODE, TS>;
   const int grid = persistent_grid(k, C::NT, a.ntiles);
   if (grid <= 0) return hipSuccess;
+  a.xcd = ((P.tile_sel >> 2) & 1) && grid % 8 == 0;
   hipLaunchKernelGGL(k, dim3(grid), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
@@ -690,7 +707,7 @@ hipError_t launch_c2r_ts(const Pass &P, const PassIO &io, const float2 *tw, hipS
 // runs schedule 0.
 #define PSN_TILE_DISPATCH(LAUNCH, FITS, ...)                                   \
   if constexpr (MODE == MODE_FP32) {                                           \
-    switch (P.tile_sel) {                                                      \
+    switch (P.tile_sel & 3) {                                                  \
       case 1: if constexpr (FITS(1)) return LAUNCH<__VA_ARGS__, 1>(P, io, tw, s); break; \
       case 2: if constexpr (FITS(2)) return LAUNCH<__VA_ARGS__, 2>(P, io, tw, s); break; \
       case 3: if constexpr (FITS(3)) return LAUNCH<__VA_ARGS__, 3>(P, io, tw, s); break; \
@@ -742,6 +759,7 @@ hipError_t launch_conv(const Pass &P, const PassIO &io, const float2 *tw, const 
   auto k = conv_kernel<L, PC, MODE>;
   const int blocks = persistent_grid(k, kConvWaves * 64, int(need < (1 << 30) ? need : (1 << 30)));
   if (blocks <= 0) return hipSuccess;
+  a.xcd = ((P.tile_sel >> 2) & 1) && blocks % 8 == 0;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(kConvWaves * 64), 0, s, a);
   return hipGetLastError();
 }
@@ -813,8 +831,9 @@ hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const 
   return hipErrorInvalidValue;
 }
 
-int pass_tile_lines(const Pass &P, int ts, int mode) {
-  if (ts < 0 || ts >= kTileSchedules) return 0;
+int pass_tile_lines(const Pass &P, int sched, int mode) {
+  if (sched < 0 || sched >= kSchedules) return 0;
+  const int ts = sched & 3;  // the XCD-order bit does not change the tile
   if (mode != MODE_FP32 && ts != 0) return 0;
   switch (P.L) {
 #define PSN_CASE(LL) \

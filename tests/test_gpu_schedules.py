@@ -1,7 +1,8 @@
-"""GPU: tile schedules and the autotuner.
+"""GPU: pass schedules (tile width, XCD workgroup order) and the autotuner.
 
-A tile schedule only changes which lines a workgroup stages together, so
-every compiled schedule must give results bitwise equal to schedule 0 (whose
+A schedule only changes which lines a workgroup stages together and where
+it runs, so every compiled schedule must give results bitwise equal to
+schedule 0 (whose
 parity against the oracle the parity tests establish), on regular and ragged
 tiles.  The autotuner must leave a valid schedule and equal results.
 """
@@ -63,8 +64,8 @@ def test_every_tile_schedule_is_bitwise_equal(torch_dev, n, bc):
     ref = plan.solve(r).clone()
     compiled = _compiled(plan)
     print(f"{n} bc={bc}: compiled schedules per pass {compiled}", flush=True)
-    assert compiled[2] == [0]  # the fused conv pass has no tile schedule
-    assert all(0 in c for c in compiled)
+    assert compiled[2] == [0, 4]  # the fused conv pass: no tile width, both orders
+    assert all(0 in c and 4 in c for c in compiled)  # the XCD order works everywhere
     # one pass at a time, then all passes together
     trials = []
     for k in range(5):
@@ -97,6 +98,8 @@ def test_schedule_rejects_bad_values(torch_dev):
     with pytest.raises(P.PoissonError) as e:
         split.set_schedule([1, 0, 0, 0, 0])
     assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
+    split.set_schedule([4] * 5)  # width 0 in XCD order is compiled for split modes
+    assert list(split.schedule[0]) == [4] * 5
 
 
 @pytest.mark.parametrize("n,bc", [((256, 256, 256), 7), ((64, 96, 48), 3)])
@@ -130,7 +133,7 @@ def test_batch_tune_keeps_results(torch_dev):
     scratch = [torch.empty_like(r) for r in rhos]
     mb = B.tune(rhos, scratch, reps=2)
     print(f"batch tune: {mb} MiB per launch", flush=True)
-    assert mb in (32.0, 64.0, 96.0, 128.0, 192.0, 256.0)
+    assert mb in (32.0, 64.0, 96.0, 128.0, 192.0, 256.0, 384.0, 512.0)
     Vs = [torch.empty_like(r) for r in rhos]
     B.solve(rhos, Vs)
     torch.cuda.synchronize()
