@@ -146,6 +146,38 @@ def test_host_buffer_solves(torch_dev):
         assert torch.equal(outs2[i], ref[i]), i
 
 
+# extreme lengths: the longest compiled (1024, 768) and the shortest (4) FFT
+# lines, on each kind of axis, and n = 2 on a free axis
+EXTREME = [((512, 6, 8), 7), ((384, 8, 6), 7), ((2, 4, 2), 7), ((1024, 4, 6), 0),
+           ((768, 4, 4), 6), ((4, 512, 4), 2), ((6, 4, 1024), 0), ((4, 6, 384), 3)]
+
+
+@pytest.mark.parametrize("n,bc", EXTREME)
+def test_extreme_lengths(torch_dev, n, bc):
+    rho = _density(n, bc, seed=500 + bc, count=3)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"{n} bc={bc}")
+
+
+@pytest.mark.parametrize("bc", [7, 3, 2, 0])
+def test_zero_density_gives_zero(torch_dev, bc):
+    n = (24, 32, 12)
+    V, _ = _gpu_solve(torch_dev, n, bc, np.zeros((n[2], n[1], n[0]), np.float32))
+    assert not np.any(V), bc  # exactly zero, no rounding residue
+
+
+@pytest.mark.parametrize("bc", range(8))
+def test_point_charge(torch_dev, bc):
+    """A single grid charge: every Fourier mode carries the same weight."""
+    n = (16, 24, 12)
+    rho = np.zeros((n[2], n[1], n[0]), np.float32)
+    rho[5, 7, 3] = 1.0 / H ** 3
+    if bc == 0:
+        rho -= rho.mean(dtype=np.float64)  # periodic: the k = 0 mode is projected out
+    V, _ = _gpu_solve(torch_dev, n, bc, rho)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"point charge bc={bc}")
+
+
 def test_kernel_set_from_oracle_octant(torch_dev):
     """poisson_kernel_set with the oracle's octant gives the same solve."""
     n, bc = (32, 24, 48), 3
