@@ -526,8 +526,11 @@ constexpr int kConvWaves = 4;
 // The walk is wavefront-uniform (a group without work transforms the first
 // line of the array and stores nothing) so matrix-core stages always run on
 // whole wavefronts.  With one line per wavefront the walk is scalar.
+template <int L> constexpr int conv_min_waves() { return Shape<L>::E >= 24 ? 2 : 1; }
+
 template <int L, bool PC, int MODE>
-__global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
+__global__ __launch_bounds__(kConvWaves * 64)
+__attribute__((amdgpu_waves_per_eu(conv_min_waves<L>()))) void conv_kernel(ConvParams a) {
   constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T, KR = L / 2 + 1;
   constexpr int SLOTS = line_lds_slots<L>();
   __shared__ float2 smem[kConvWaves * LPW * SLOTS];
@@ -604,18 +607,30 @@ __global__ __launch_bounds__(kConvWaves * 64) void conv_kernel(ConvParams a) {
     }
   };
 
-  Item A, B;
+  Item A;
   fetch(A);
   advance();
-  while (true) {
-    fetch(B);
-    advance();
-    process(A);
-    if (!__any(B.live)) break;
-    fetch(A);
-    advance();
-    process(B);
-    if (!__any(A.live)) break;
+  if constexpr (E >= 24) {
+    // 24 elements per lane: two items would need about 260 registers and
+    // leave one wavefront per SIMD; one item, two wavefronts per SIMD
+    while (true) {
+      process(A);
+      fetch(A);
+      advance();
+      if (!__any(A.live)) break;
+    }
+  } else {
+    Item B;
+    while (true) {
+      fetch(B);
+      advance();
+      process(A);
+      if (!__any(B.live)) break;
+      fetch(A);
+      advance();
+      process(B);
+      if (!__any(A.live)) break;
+    }
   }
 }
 
