@@ -710,9 +710,16 @@ template <typename F> int time_enqueue(F &&enqueue, hipStream_t s, int reps, dou
 int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float *const *V,
                      void *ws, hipStream_t s, int reps, double *pass_ms) {
   auto solve = [&] { return enqueue_passes(P, count, rho, V, ws, 0, 4, s); };
+  int start[5];
+  for (int k = 0; k < 5; ++k) start[k] = P->g.pass[k].tile_sel;
   double best = 0;
   int rc = time_enqueue(solve, s, reps, &best);
   if (rc) return rc;
+  // small solves are launch-bound and noisy: time at least ~2 ms per round
+  if (best > 0) reps = std::max(reps, std::min(1000, int(std::ceil(2.0 / best))));
+  rc = time_enqueue(solve, s, reps, &best);
+  if (rc) return rc;
+  const double start_ms = best;
   for (int k = 0; k < 5; ++k) {
     psn::Pass &pass = P->g.pass[k];
     const int keep = pass.tile_sel;
@@ -732,6 +739,20 @@ int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float
       }
     }
     pass.tile_sel = best_sel;
+  }
+  // keep the new schedule only if it still beats the starting one when both
+  // are timed again now
+  bool changed = false;
+  for (int k = 0; k < 5; ++k) changed = changed || P->g.pass[k].tile_sel != start[k];
+  if (changed) {
+    int tuned[5];
+    for (int k = 0; k < 5; ++k) tuned[k] = P->g.pass[k].tile_sel;
+    double t_tuned = 0, t_start = 0;
+    if ((rc = time_enqueue(solve, s, reps, &t_tuned))) return rc;
+    for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = start[k];
+    if ((rc = time_enqueue(solve, s, reps, &t_start))) return rc;
+    const bool keep = t_tuned < 0.99 * std::min(t_start, start_ms);
+    for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = keep ? tuned[k] : start[k];
   }
   if (!pass_ms) return POISSON_OK;
   hipEvent_t ev[6] = {};
