@@ -274,6 +274,72 @@ def test_full_free256(torch_dev):
     assert np.max(np.abs(got - direct)) <= ELEM * np.max(np.abs(ref))
 
 
+def test_max_size_periodic_1024_closed_form(torch_dev):
+    """The largest grid (1024^3 periodic: the biggest intermediates, 537M
+    complex elements each) against the closed form V = -rho/|k|^2 of a
+    single cosine mode (Eq. 3 with the spectral wave numbers)."""
+    torch = torch_dev
+    n = (1024, 1024, 1024)
+    f = (3, 5, 2)
+    L = [v * H for v in n]
+    ax = [torch.arange(v, device="cuda", dtype=torch.float64) * H for v in n]
+    cx = torch.cos(2 * np.pi * f[0] * ax[0] / L[0])
+    cy = torch.cos(2 * np.pi * f[1] * ax[1] / L[1])
+    cz = torch.cos(2 * np.pi * f[2] * ax[2] / L[2])
+    k2 = sum((2 * np.pi * f[j] / L[j]) ** 2 for j in range(3))
+    rho = (cz[:, None, None] * cy[None, :, None] * cx[None, None, :]).float()
+    del ax
+    plan = P.Plan(n, 0, H)
+    V = plan.solve(rho)
+    torch.cuda.synchronize()
+    plan.close()
+    # exact answer for the float32-rounded density: the mode's amplitude
+    # scales by -1/|k|^2; rounding of rho adds other modes of relative size
+    # ~1e-8, so compare against -rho/|k|^2 itself
+    num = torch.linalg.vector_norm(V.double() + rho.double() / k2)
+    den = torch.linalg.vector_norm(rho.double() / k2)
+    err = float(num / den)
+    print(f"periodic 1024^3 cosine mode: relL2 {err:.3e}", flush=True)
+    assert err <= 1e-6
+
+
+def test_max_size_free512_samples(torch_dev):
+    """512^3 free (FFT grid 1024^3, the longest lines) at sampled points,
+    each a float64 direct sum of Eq. 2 on the GPU (no FFT)."""
+    torch = torch_dev
+    n = (512, 512, 512)
+    gs = draw_gaussians(n, H, 4, (2.0, 6.0), 77)
+    ax = [torch.arange(v, device="cuda", dtype=torch.float64) * H for v in n]
+    rho = torch.zeros((n[2], n[1], n[0]), device="cuda", dtype=torch.float64)
+    for spec in gs:
+        c, sig, q = spec.center, spec.sigma, spec.charge
+        g = [torch.exp(-(ax[j] - c[j]) ** 2 / (2 * sig * sig)) for j in range(3)]
+        rho += q * (2 * np.pi * sig * sig) ** -1.5 * (g[2][:, None, None] * g[1][None, :, None]
+                                                       * g[0][None, None, :])
+    rho = rho.float()
+    plan = P.Plan(n, 7, H)
+    V = plan.solve(rho)
+    torch.cuda.synchronize()
+    plan.close()
+    z = torch.arange(n[2], device="cuda", dtype=torch.float64)[:, None, None]
+    y = torch.arange(n[1], device="cuda", dtype=torch.float64)[None, :, None]
+    x = torch.arange(n[0], device="cuda", dtype=torch.float64)[None, None, :]
+    r64 = rho.double()
+    pts = [(0, 0, 0), (511, 511, 511), (256, 100, 400), (17, 300, 255), (511, 0, 256)]
+    got, want = [], []
+    for (i1, i2, i3) in pts:
+        m2 = (x - i1) ** 2 + (y - i2) ** 2 + (z - i3) ** 2
+        k = torch.where(m2 > 0, -H * H / (4 * np.pi * torch.sqrt(torch.clamp(m2, min=1))),
+                        torch.full_like(m2, -(H * H / (4 * np.pi)) * 2.837297479480619))
+        want.append(float(torch.sum(k * r64)))
+        got.append(float(V[i3, i2, i1]))
+        del m2, k
+    scale = float(torch.max(torch.abs(V)))
+    d = np.max(np.abs(np.array(got) - np.array(want))) / scale
+    print(f"free 512^3 direct-sum samples: max |dV| / max|V| = {d:.3e}", flush=True)
+    assert d <= ELEM
+
+
 @pytest.mark.parametrize("name", ["wire192x192x384", "surface384x192x384"])
 def test_full_mixed_bc_large(torch_dev, name):
     n, bc, rho = workload_density(name)
