@@ -130,10 +130,17 @@ __device__ __forceinline__ f4_t dft8_mfma(const DftOperand<MODE> &W, const float
   return acc;
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
+// Maximum of a non-negative value over lanes l, l ^ 16, l ^ 32, l ^ 48 (one
+// matrix column).  Non-negative floats order like their bit patterns, so an
+// integer max needs no NaN canonicalization, and the two lane exchanges are
+// the CDNA4 row swaps (VALU, no LDS crossbar): permlane32_swap pairs lane l
+// with l ^ 32, permlane16_swap lane l with l ^ 16.
+__device__ __forceinline__ float column_max(float v) {
+  unsigned u = __float_as_uint(v);
+  const auto s32 = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  u = max(s32[0], s32[1]);
+  const auto s16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __uint_as_float(max(s16[0], s16[1]));
 }
 
 // Twiddle product with one fixed rounding order (one product rounded, the
@@ -192,7 +199,9 @@ __device__ __forceinline__ void split_stage(float2 *__restrict__ wl, const Split
         if constexpr (S > 0) a = cmul_tw_fixed<INV>(a, tw((jj[b] % NS) * (2 * gq + u) * STEP));
         x[b][2 * u] = a.x;
         x[b][2 * u + 1] = a.y;
-        cmax[b] = fmaxf(cmax[b], fmaxf(fabsf(a.x), fabsf(a.y)));
+        // |x| as bits: non-negative floats order like unsigned integers
+        const unsigned ax = __float_as_uint(a.x) & 0x7fffffffu, ay = __float_as_uint(a.y) & 0x7fffffffu;
+        cmax[b] = __uint_as_float(max(__float_as_uint(cmax[b]), max(ax, ay)));
       }
     }
     wave_lds_fence();  // all inputs read before outputs overwrite them
@@ -201,9 +210,7 @@ __device__ __forceinline__ void split_stage(float2 *__restrict__ wl, const Split
       // one power of two per butterfly (matrix column): its 16 entries sit
       // in lanes n, n + 16, n + 32, n + 48; left products by W commute with
       // column scaling, so the scale is undone exactly on the output column
-      float m = cmax[b];
-      m = fmaxf(m, __shfl_xor(m, 16, 64));
-      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      const float m = column_max(cmax[b]);
       int e2;
       (void)frexpf(m, &e2);  // |x| * 2^-e2 < 1
       // keep both factors finite: columns below 2^-100 (denormal tails of a
