@@ -55,8 +55,11 @@ def build(jobs=None, verbose=False):
     # one object per length group, each instantiating the launchers for its lengths
     for L in PASS_LENGTHS:
         for mode in (0, 1, 2):  # float32, split fp16, split bf16
+            # split modes: matrix-core results straight into VGPRs (no
+            # accumulator-register reads after every product)
+            extra = ("-mllvm", "-amdgpu-mfma-vgpr-form=1") if mode else ()
             tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, f"passes_{L}_{mode}.o"),
-                          (f"-DPSN_ONLY_LENGTH={L}", f"-DPSN_ONLY_MODE={mode}")))
+                          (f"-DPSN_ONLY_LENGTH={L}", f"-DPSN_ONLY_MODE={mode}", *extra)))
     tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, "passes_dispatch.o"),
                   ("-DPSN_DISPATCH_ONLY=1",)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
