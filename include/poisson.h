@@ -227,18 +227,19 @@ int poisson_plan_set_schedule(poisson_plan_t plan, const int tile_sel[5]);
 int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lines[5]);
 
 /* Autotuner: coordinate descent over the five passes.  For each pass, every
- * compiled schedule is timed as whole solves on this device (reps solves
- * per candidate after a warm-up, best of two rounds, hipEvents on `stream`),
- * so a candidate is charged for what it leaves in the caches for the next
- * pass; it replaces the current choice only if the solve gets at least 1%
- * faster.  Runs solves on rho_dev and V_dev: V_dev (and the workspace)
- * receive scratch values.  pass_ms (may be NULL) receives the chosen
- * schedule's per-pass times.  reps <= 0 means 10.  Needs K^F and a
- * workspace; synchronous. */
+ * compiled schedule is timed as whole solves on this device (at least reps
+ * solves and about 2 ms per round after a warm-up, best of two rounds,
+ * hipEvents on `stream`), so a candidate is charged for what it leaves in
+ * the caches for the next pass; it replaces the current choice only if the
+ * solve gets at least 1% faster, and the final schedule is kept only if it
+ * still beats the starting one when both are timed again.  Runs solves on
+ * rho_dev and V_dev: V_dev (and the workspace) receive scratch values.
+ * pass_ms (may be NULL) receives the chosen schedule's per-pass times.
+ * reps <= 0 means 10.  Needs K^F and a workspace; synchronous. */
 int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, int reps,
                       double pass_ms[5], void *stream);
 
-/* Autotuner for a batch: tunes each distinct plan's tile schedules on its
+/* Autotuner for a batch: tunes each distinct plan's schedules on its
  * first chunk, then times whole batch solves for intermediates budgets of
  * 32..512 MiB and keeps the fastest (chunk_mb, may be NULL, receives it).
  * The arrays are those of poisson_batch_solve; V receives scratch values.
