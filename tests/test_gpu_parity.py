@@ -159,6 +159,14 @@ def test_extreme_lengths(torch_dev, n, bc):
     _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"{n} bc={bc}")
 
 
+@pytest.mark.parametrize("prec", [P.POISSON_SPLIT_FP16, P.POISSON_SPLIT_BF16])
+@pytest.mark.parametrize("n,bc", EXTREME)
+def test_split_extreme_lengths(torch_dev, n, bc, prec):
+    rho = _density(n, bc, seed=500 + bc, count=3)
+    V, _ = _gpu_solve(torch_dev, n, bc, rho, precision=prec)
+    _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"split{prec} {n} bc={bc}")
+
+
 @pytest.mark.parametrize("bc", [7, 3, 2, 0])
 def test_zero_density_gives_zero(torch_dev, bc):
     n = (24, 32, 12)
