@@ -158,7 +158,13 @@ int poisson_solve(poisson_plan_t plan, const float *rho_dev, float *V_dev, void 
  * (the step list of Section 3 with the transposes folded into the passes).
  * Passes exchange data through the plan's workspace, so a later range sees
  * the intermediates an earlier one left; running 0..4 equals poisson_solve.
- * For per-pass timing and inspection. */
+ * For per-pass timing and inspection.  Workspace layout (complex64, axis
+ * order (p, q, r), H = S_p/2+1): A1 at offset 0, H*N_q*N_r elements, with
+ * t1 fastest (t1 = q if p is x, else x), then p, then the third axis,
+ * written by pass 0 and 3; A2 at the next multiple of 256 bytes,
+ * H*S_q*N_r elements, r fastest, then q, then p, written by passes 1 and 2.
+ * The conv pass multiplies by K^F/(S1 S2 S3); inverse transforms are
+ * unnormalized. */
 int poisson_solve_passes(poisson_plan_t plan, const float *rho_dev, float *V_dev, int first,
                          int last, void *stream);
 

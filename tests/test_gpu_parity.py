@@ -186,6 +186,79 @@ def test_point_charge(torch_dev, bc):
     _check(V, oracle.solve(rho.astype(np.float64), bc, H), f"point charge bc={bc}")
 
 
+@pytest.mark.parametrize("n,bc", [((24, 32, 16), 7), ((24, 32, 16), 3), ((24, 16, 32), 4)])
+def test_each_pass_against_numpy_fft(torch_dev, n, bc):
+    """Pass by pass (Section 3's steps with the transposes folded into the
+    layouts): each GPU pass output, read from a caller-owned workspace,
+    against numpy's FFT of the GPU's previous intermediate, in float64.
+    Order (x, y, z) is forced, so the layouts are
+      A1[z][kx][y] (y fastest) after P1 and P4, A2[kx][ky][z] after P2, P3."""
+    torch = torch_dev
+    n1, n2, n3 = n
+    plan = P.Plan(n, bc, H, axis_order=(0, 1, 2))
+    S1, S2, S3 = plan.S
+    Hx = S1 // 2 + 1
+    ws_bytes = plan.info["workspace_bytes"]
+    ws = torch.zeros(ws_bytes, dtype=torch.uint8, device="cuda")
+    P.poisson_set_workspace(plan.handle, ws, ws_bytes)
+    a1_bytes = (Hx * n2 * n3 * 8 + 255) // 256 * 256
+    rho = _density(n, bc, seed=600 + bc)
+    r = torch.from_numpy(rho).cuda()
+    V = torch.empty_like(r)
+    stream = torch.cuda.current_stream()
+    kf = oracle.kernel_fourier(n, bc, H)  # (S3, S2, S1)
+
+    def a1():
+        b = ws[:Hx * n2 * n3 * 8].cpu().numpy().view(np.complex64)
+        return b.reshape(n3, Hx, n2).astype(np.complex128)
+
+    def a2():
+        b = ws[a1_bytes:a1_bytes + Hx * S2 * n3 * 8].cpu().numpy().view(np.complex64)
+        return b.reshape(Hx, S2, n3).astype(np.complex128)
+
+    def rel(got, want):
+        return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+    def run(k):
+        P.poisson_solve_passes(plan.handle, r, V, k, k, stream)
+        torch.cuda.synchronize()
+
+    # P1: real-to-complex along x of the zero-padded density
+    run(0)
+    pad = np.zeros((n3, n2, S1))
+    pad[:, :, :n1] = rho
+    want = np.fft.rfft(pad, axis=2).transpose(0, 2, 1)          # [z][kx][y]
+    e1 = rel(a1(), want)
+    # P2: forward along y, zero-padded
+    prev = a1()
+    run(1)
+    pad = np.zeros((n3, Hx, S2), complex)
+    pad[:, :, :n2] = prev
+    want = np.fft.fft(pad, axis=2).transpose(1, 2, 0)           # [kx][ky][z]
+    e2 = rel(a2(), want)
+    # P3: forward along z, times K^F / (S1 S2 S3), unnormalized inverse, crop
+    prev = a2()
+    run(2)
+    pad = np.zeros((Hx, S2, S3), complex)
+    pad[:, :, :n3] = prev
+    kz = kf[:, :, :Hx].transpose(2, 1, 0) / (S1 * S2 * S3)     # [kx][ky][kz]
+    want = (np.fft.ifft(kz * np.fft.fft(pad, axis=2), axis=2) * S3)[:, :, :n3]
+    e3 = rel(a2(), want)
+    # P4: unnormalized inverse along y, crop
+    prev = a2()
+    run(3)
+    want = (np.fft.ifft(prev, axis=1) * S2)[:, :n2, :].transpose(2, 0, 1)  # [z][kx][y]
+    e4 = rel(a1(), want)
+    # P5: complex-to-real along x, unnormalized, crop
+    prev = a1()
+    run(4)
+    want = (np.fft.irfft(prev.transpose(0, 2, 1), n=S1, axis=2) * S1)[:, :, :n1]
+    e5 = rel(V.cpu().numpy().astype(np.float64), want)
+    print(f"{n} bc={bc} per-pass relL2: {e1:.2e} {e2:.2e} {e3:.2e} {e4:.2e} {e5:.2e}", flush=True)
+    for e in (e1, e2, e3, e4, e5):
+        assert e <= 5e-7  # one float32 pass: a few units of 2^-24
+
+
 def test_kernel_set_from_oracle_octant(torch_dev):
     """poisson_kernel_set with the oracle's octant gives the same solve."""
     n, bc = (32, 24, 48), 3
