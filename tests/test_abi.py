@@ -176,6 +176,25 @@ def test_null_and_bad_host_arguments():
     assert lib.poisson_plan_destroy(None) == 0
 
 
+def test_null_handles_of_the_later_entry_points():
+    """Schedules, tuning, host-buffer solves and plan queries reject a NULL
+    plan or array before touching any device."""
+    lib = P.load_library()
+    E = P._lib.POISSON_E_ARG
+    sel = (ctypes.c_int * 5)()
+    assert lib.poisson_plan_set_schedule(None, sel) == E
+    assert lib.poisson_plan_get_schedule(None, sel, sel) == E
+    assert lib.poisson_plan_tune(None, None, None, 0, None, None) == E
+    assert lib.poisson_batch_tune(None, None, None, 0, None, None) == E
+    assert lib.poisson_solve_host(None, None, None, None) == E
+    assert lib.poisson_solve_host_many(None, 1, None, None, None) == E
+    assert lib.poisson_plan_info(None, None, None, None, None) == E
+    out = ctypes.c_void_p()
+    bad = (ctypes.c_int * 3)(0, 0, 1)
+    assert lib.poisson_plan_ordered(ctypes.byref(out), 8, 8, 8, 7, 0.3, 0, bad) == E
+    assert out.value is None
+
+
 def test_batch_rejects_one_bad_entry_before_any_device_call():
     with pytest.raises(P.PoissonError) as e:
         P.poisson_batch_create([(8, 8, 8), (5, 8, 8)], [7, 7], [0.3, 0.3])
