@@ -712,13 +712,18 @@ int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float
   auto solve = [&] { return enqueue_passes(P, count, rho, V, ws, 0, 4, s); };
   int start[5];
   for (int k = 0; k < 5; ++k) start[k] = P->g.pass[k].tile_sel;
+  // a failure leaves the schedules as they were
+  auto restore = [&](int code) {
+    for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = start[k];
+    return code;
+  };
   double best = 0;
   int rc = time_enqueue(solve, s, reps, &best);
   if (rc) return rc;
   // small solves are launch-bound and noisy: time at least ~2 ms per round
   if (best > 0) reps = std::max(reps, std::min(1000, int(std::ceil(2.0 / best))));
   rc = time_enqueue(solve, s, reps, &best);
-  if (rc) return rc;
+  if (rc) return restore(rc);
   const double start_ms = best;
   for (int k = 0; k < 5; ++k) {
     psn::Pass &pass = P->g.pass[k];
@@ -729,10 +734,7 @@ int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float
       pass.tile_sel = sel;
       double t = 0;
       rc = time_enqueue(solve, s, reps, &t);
-      if (rc) {
-        pass.tile_sel = keep;
-        return rc;
-      }
+      if (rc) return restore(rc);
       if (t < 0.99 * best) {
         best = t;
         best_sel = sel;
@@ -748,9 +750,9 @@ int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float
     int tuned[5];
     for (int k = 0; k < 5; ++k) tuned[k] = P->g.pass[k].tile_sel;
     double t_tuned = 0, t_start = 0;
-    if ((rc = time_enqueue(solve, s, reps, &t_tuned))) return rc;
+    if ((rc = time_enqueue(solve, s, reps, &t_tuned))) return restore(rc);
     for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = start[k];
-    if ((rc = time_enqueue(solve, s, reps, &t_start))) return rc;
+    if ((rc = time_enqueue(solve, s, reps, &t_start))) return restore(rc);
     const bool keep = t_tuned < 0.99 * std::min(t_start, start_ms);
     for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = keep ? tuned[k] : start[k];
   }
@@ -824,7 +826,15 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
     int rc = tune_plan_passes(B->plans[u], cnt, r.data(), v.data(), B->ws, s, reps, nullptr);
     if (rc) return rc;
   }
-  // 2. the intermediates budget of one launch, timed on the whole batch
+  // 2. the intermediates budget of one launch, timed on the whole batch; a
+  // failure restores the chunking it started from (a grown workspace stays)
+  const std::vector<int> chunk0 = B->chunk;
+  const double mb0 = B->chunk_mb;
+  auto restore = [&](int code) {
+    B->chunk = chunk0;
+    B->chunk_mb = mb0;
+    return code;
+  };
   std::vector<double> budgets = {B->chunk_mb};  // the current budget first
   for (double mb : {32.0, 64.0, 96.0, 128.0, 192.0, 256.0, 384.0, 512.0})
     if (mb != B->chunk_mb) budgets.push_back(mb);
@@ -834,7 +844,8 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
       std::vector<int> chunk;
       const size_t need = batch_chunks(B, mb, chunk);
       if (need > B->ws_bytes) {
-        PSN_TRY_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        hipError_t se = hipStreamSynchronize(s);
+        if (se != hipSuccess) return restore(hip_fail(se, "hipStreamSynchronize"));
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, need);
         if (e != hipSuccess) {
@@ -848,7 +859,7 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
       B->chunk = chunk;
       double t = 0;
       int rc = time_enqueue([&] { return poisson_batch_solve(B, rho, V, stream); }, s, reps, &t);
-      if (rc) return rc;
+      if (rc) return restore(rc);
       if (t < 0.99 * best) {
         best = t;
         best_mb = mb;
