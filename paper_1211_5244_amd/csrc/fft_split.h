@@ -176,12 +176,19 @@ template <int MODE> struct SplitOps {
 
 // One stage, LDS to LDS.  `wl` is the wavefront's first line region; line l
 // of the wavefront lives at wl + l * line_lds_slots<L>().
-template <int L, int S, bool INV, int MODE>
+// ZHI: the line's upper half is zero on entry (a zero-padded line); CROP:
+// only the first half of the outputs is kept.  A radix-8 stage runs on the
+// matrix cores except where it touches half the data: the first stage of a
+// zero-padded transform (four of eight legs are zero) and the last stage of
+// a cropped one.  Those stay on the vector ALUs in float32, where they cost
+// less than the split and scaling around a matrix product.
+template <int L, int S, bool INV, int MODE, bool ZHI = false, bool CROP = false>
 __device__ __forceinline__ void split_stage(float2 *__restrict__ wl, const SplitTwiddles<L> &tw,
                                             const SplitOps<MODE> &ops, int lane) {
   constexpr int E = Shape<L>::E, R = Shape<L>::R[S], NS = span<L>(S), T = kT<L>;
   constexpr int SLOTS = line_lds_slots<L>(), NB = L / R, STEP = L / (NS * R);
-  if constexpr (R == 8) {
+  constexpr bool HALF = (S == 0 && ZHI) || (S + 1 == Shape<L>::NR && CROP);
+  if constexpr (R == 8 && !HALF) {
     const int gq = lane / 16, n = lane % 16;
     float x[E / 2][4];
     int line[E / 2], jj[E / 2];
@@ -245,19 +252,19 @@ __device__ __forceinline__ void split_stage(float2 *__restrict__ wl, const Split
 #pragma unroll
         for (int m = 1; m < R; ++m) a[m] = cmul_tw<INV>(a[m], tw((j % NS) * m * STEP));
       }
-      dft<R, INV>(a);
+      dft<R, INV, ZHI && S == 0>(a);
       const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
       for (int m = 0; m < R; ++m) ln[lds_pad(base + m * NS)] = a[m];
     }
   }
   wave_lds_fence();
-  if constexpr (S + 1 < Shape<L>::NR) split_stage<L, S + 1, INV, MODE>(wl, tw, ops, lane);
+  if constexpr (S + 1 < Shape<L>::NR) split_stage<L, S + 1, INV, MODE, ZHI, CROP>(wl, tw, ops, lane);
 }
 
 // Transform of the wavefront's LPW lines.  v holds lane t's strided elements
 // of its line (as in fft_line); `wl` is the wavefront's LDS line block.
-template <int L, bool INV, int MODE>
+template <int L, bool INV, int MODE, bool ZHI = false, bool CROP = false>
 __device__ __forceinline__ void fft_line_split(float2 (&v)[Shape<L>::E], const SplitTwiddles<L> &tw,
                                                const SplitOps<MODE> &ops, float2 *__restrict__ wl,
                                                int lane) {
@@ -267,7 +274,7 @@ __device__ __forceinline__ void fft_line_split(float2 (&v)[Shape<L>::E], const S
 #pragma unroll
   for (int i = 0; i < E; ++i) ln[lds_pad(t + T * i)] = v[i];
   wave_lds_fence();
-  split_stage<L, 0, INV, MODE>(wl, tw, ops, lane);
+  split_stage<L, 0, INV, MODE, ZHI, CROP>(wl, tw, ops, lane);
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = ln[lds_pad(t + T * i)];
   wave_lds_fence();

@@ -150,17 +150,19 @@ template <int L, int MODE> struct LineEngine {
     tw.load(tab, lane);
     ops.init(lane);
   }
-  // ZHI (upper half of the inputs zero) is not used by the matrix-core stages
-  template <bool INV, bool ZHI = false>
+  // ZHI: upper half of the inputs zero; CROP: only the first half of the
+  // outputs is used (those stages run on the vector ALUs, see split_stage)
+  template <bool INV, bool ZHI = false, bool CROP = false>
   __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
                                       int lane) {
-    fft_line_split<L, INV, MODE>(v, tw, ops, wave_lines, lane);
+    fft_line_split<L, INV, MODE, ZHI, CROP>(v, tw, ops, wave_lines, lane);
   }
 };
 template <int L> struct LineEngine<L, MODE_FP32> {
   Twiddles<L> tw;
   __device__ __forceinline__ void init(const float2 *tab, int lane) { tw.load(tab, lane % kT<L>); }
-  template <bool INV, bool ZHI = false>
+  // (a cropped output needs nothing here: unstored outputs are dead code)
+  template <bool INV, bool ZHI = false, bool CROP = false>
   __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
                                       int lane) {
     fft_line<L, INV, ZHI>(v, tw, line, lane % kT<L>);
@@ -299,7 +301,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    eng.template run<INV, PAD>(v, xch, wave_lines, lane);
+    eng.template run<INV, PAD, CROP>(v, xch, wave_lines, lane);
 
     if constexpr (OUT_TILED) {
       __syncthreads();  // every line is done exchanging
@@ -475,7 +477,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
     }
     __syncthreads();
 
-    eng.template run<true>(v, xch, wave_lines, lane);
+    eng.template run<true, false, CROP>(v, xch, wave_lines, lane);
 
     if constexpr (OUT_TILED) {
       __syncthreads();
@@ -599,7 +601,7 @@ __attribute__((amdgpu_waves_per_eu(conv_min_waves<L>()))) void conv_kernel(ConvP
     eng.template run<false, PC>(it.v, xch, wave_lines, lane);
 #pragma unroll
     for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
-    eng.template run<true>(it.v, xch, wave_lines, lane);
+    eng.template run<true, false, PC>(it.v, xch, wave_lines, lane);
     if (it.live) {
 #pragma unroll
       for (int i = 0; i < E; ++i)
