@@ -73,7 +73,17 @@ def cpu_baseline(rho32, n, bc, reps=3, workers=None, warmup=True):
         V = oracle.solve(rho64, bc, H, kf=kf, workers=workers)
         t.append(time.perf_counter() - t0)
     med = float(np.median(t))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return V, {"value": 1.0 / med, "unit": "solves/s", "cores": workers, "kind": "oracle",
+               "cpu_model": model,
                "sample": f"{reps} whole FP64 solves of the same workload"
                          f"{' after 1 warm-up' if warmup else ''} "
                          f"(scipy.fft, workers={workers}, K^F prebuilt); median {med:.3f} s"}
