@@ -191,7 +191,7 @@ __device__ __forceinline__ float ld_stream(const float *p) { return __builtin_no
 // (grid a multiple of 8), workgroup b takes the virtual index that gives
 // each XCD a contiguous run of tiles per round: XCD x's j-th workgroup gets
 // x * (G / 8) + j, so neighbouring tiles, which read neighbouring row
-// segments, share an L2 and stream whole DRAM rows.
+// segments, share an L2.  The autotuner decides per pass whether it pays.
 __device__ __forceinline__ int block_order(int xcd) {
   const int b = blockIdx.x, G = gridDim.x;
   return xcd ? (b & 7) * (G >> 3) + (b >> 3) : b;
@@ -528,6 +528,7 @@ constexpr int kConvWaves = 4;
 // The walk is wavefront-uniform (a group without work transforms the first
 // line of the array and stores nothing) so matrix-core stages always run on
 // whole wavefronts.  With one line per wavefront the walk is scalar.
+// 24-element lanes: two wavefronts per SIMD (see the single line buffer below)
 template <int L> constexpr int conv_min_waves() { return Shape<L>::E >= 24 ? 2 : 1; }
 
 template <int L, bool PC, int MODE>
