@@ -146,6 +146,10 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     t_loop = timed(loop)
     ref = [v.clone() for v in Vs]
     t_batch = timed(batched)
+
+    def max_rel_diff():  # largest relative L2 difference from the per-solve loop
+        return max(float((a.double() - b.double()).norm() / a.double().norm()) for a, b in zip(ref, Vs))
+
     same = all(torch.equal(a, b) for a, b in zip(ref, Vs))
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream(dev)
@@ -159,7 +163,8 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     # the autotuner: tile schedules per distinct plan, then the per-launch budget
     chunk_mb = B.tune(rhos, Vs)
     t_tuned = timed(batched)
-    same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
+    # tuned schedules may use the small-grid plane kernel, equal to float32 rounding only
+    tuned_diff = max_rel_diff()
     g2 = torch.cuda.CUDAGraph()
     side.wait_stream(stream)
     with torch.cuda.stream(side):
@@ -167,9 +172,9 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
             P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream(dev))
     torch.cuda.synchronize()
     t_tuned_graph = timed(g2.replay)
-    same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
-    out = {"solves": len(items), "alg_bytes": alg, "identical_results": bool(same),
-           "tuned_chunk_mb": chunk_mb}
+    tuned_diff = max(tuned_diff, max_rel_diff())
+    out = {"solves": len(items), "alg_bytes": alg, "untuned_identical_to_loop": bool(same),
+           "tuned_max_rel_l2_vs_loop": tuned_diff, "tuned_chunk_mb": chunk_mb}
     for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph),
                     ("batched_tuned", t_tuned), ("batched_tuned_graph", t_tuned_graph)):
         out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),

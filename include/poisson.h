@@ -209,7 +209,7 @@ int poisson_batch_destroy(poisson_batch_t batch);
 /* Schedules and the autotuner.
  *
  * The radix decomposition of each FFT length is fixed.  Each pass has a
- * schedule 0..7 (0 is the default):
+ * schedule 0..15 (0 is the default):
  *  - bits 0-1, tile width: passes 0, 1, 3 and 4 stage their lines through
  *    LDS in tiles of W consecutive lines, W about 16, 8, 4 or 32 complex
  *    lines for values 0..3.  Float32 mode compiles every width that fits
@@ -219,14 +219,29 @@ int poisson_batch_destroy(poisson_batch_t batch);
  *  - bit 2, workgroup order: 1 gives each of the chip's 8 XCDs (each with
  *    its own L2) a contiguous run of tiles (or kernel rows) per round
  *    instead of every eighth one.
- * A schedule changes which lines a workgroup transforms together, where it
+ *  - bit 3, pass 2 only: run passes 1-3 as one kernel that holds each k_p
+ *    plane in LDS (the intermediate A2 never reaches HBM).  Compiled for
+ *    float32 and small grids: L_q = L_r in {32, 48, 64} periodic, {64, 96,
+ *    128} free, and (L_q, L_r) = (32, 64), (48, 96), (64, 128) with only r
+ *    free, where the q-lines are contiguous in A1.  The schedules of passes 1
+ *    and 3 are then unused.
+ * Bits 0-2 change which lines a workgroup transforms together, where it
  * runs and how long its HBM row segments are, never a line's arithmetic:
- * results are bitwise identical under every schedule. */
+ * results are bitwise identical under all of them.  Bit 3 computes the same
+ * butterflies in one kernel, where the compiler may order and contract a few
+ * float32 operations differently: results then agree with the separate
+ * passes to float32 rounding (relative L2 about 1e-7), not bitwise. */
 
-/* Set the five passes' schedules.  POISSON_E_ARG if one is outside 0..7,
+/* Set the five passes' schedules.  POISSON_E_ARG if one is outside 0..15,
  * POISSON_E_UNSUPPORTED if its tile width is not compiled for its pass
  * (then nothing changes). */
 int poisson_plan_set_schedule(poisson_plan_t plan, const int tile_sel[5]);
+
+/* The same five schedules for every distinct problem of a batch: checked
+ * against all of them first (POISSON_E_ARG / POISSON_E_UNSUPPORTED as
+ * poisson_plan_set_schedule if one of them rejects it; then nothing
+ * changes). */
+int poisson_batch_set_schedule(poisson_batch_t batch, const int tile_sel[5]);
 
 /* Current schedules and, per pass, the complex lines per tile they give
  * (0 for pass 2).  Either pointer may be NULL. */

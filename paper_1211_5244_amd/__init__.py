@@ -19,12 +19,14 @@ from ._lib import (  # noqa: F401
     POISSON_FREE_Z,
     POISSON_SPLIT_BF16,
     POISSON_SPLIT_FP16,
+    PLANE_BIT,
     TILE_SCHEDULES,
     PoissonError,
     load_library,
     poisson_batch_create,
     poisson_batch_destroy,
     poisson_batch_kernel_build,
+    poisson_batch_set_schedule,
     poisson_batch_solve,
     poisson_batch_tune,
     poisson_kernel_build,
@@ -158,6 +160,10 @@ class Batch:
         if stream is None:
             stream = torch.cuda.current_stream(rho_list[0].device)
         poisson_batch_solve(self.handle, rho_list, V_list, stream)
+
+    def set_schedule(self, tile_sel):
+        """The same five pass schedules for every distinct problem."""
+        poisson_batch_set_schedule(self.handle, tile_sel)
 
     def tune(self, rho_list, V_list, reps=0, stream=None):
         """Autotune tile schedules and the per-launch budget (V receives

@@ -34,13 +34,16 @@ EXPORTED = (
     "poisson_solve_passes", "poisson_solve_host", "poisson_solve_host_many",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
-    "poisson_plan_get_schedule", "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2",
+    "poisson_batch_set_schedule", "poisson_plan_get_schedule", "poisson_plan_tune",
+    "poisson_batch_tune", "poisson_rel_l2",
     "poisson_last_error",
 )
 
 # schedules per pass (poisson_plan_set_schedule): tile width in bits 0-1,
-# XCD-blocked workgroup order in bit 2
-TILE_SCHEDULES = 8
+# XCD-blocked workgroup order in bit 2, small-grid plane kernel in bit 3 (of
+# pass 2 only)
+TILE_SCHEDULES = 16
+PLANE_BIT = 8
 
 
 class PoissonError(RuntimeError):
@@ -93,6 +96,7 @@ def load_library(path=None):
         "poisson_batch_solve": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
         "poisson_batch_destroy": (_i, [_vp]),
         "poisson_plan_set_schedule": (_i, [_vp, ctypes.POINTER(_i)]),
+        "poisson_batch_set_schedule": (_i, [_vp, ctypes.POINTER(_i)]),
         "poisson_plan_get_schedule": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "poisson_plan_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
         "poisson_batch_tune": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
@@ -272,6 +276,11 @@ def poisson_rel_l2(v, ref, count, stream=None):
 def poisson_plan_set_schedule(plan, tile_sel):
     arr = (_i * 5)(*[int(x) for x in tile_sel])
     _check(load_library().poisson_plan_set_schedule(plan, arr))
+
+
+def poisson_batch_set_schedule(batch, tile_sel):
+    arr = (_i * 5)(*[int(x) for x in tile_sel])
+    _check(load_library().poisson_batch_set_schedule(batch, arr))
 
 
 def poisson_plan_get_schedule(plan):

@@ -62,6 +62,8 @@ def build(jobs=None, verbose=False):
                           (f"-DPSN_ONLY_LENGTH={L}", f"-DPSN_ONLY_MODE={mode}", *extra)))
     tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, "passes_dispatch.o"),
                   ("-DPSN_DISPATCH_ONLY=1",)))
+    tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, "passes_plane.o"),
+                  ("-DPSN_PLANE_ONLY=1",)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda t: _compile(*t), tasks))
     tmp = LIB + ".tmp"

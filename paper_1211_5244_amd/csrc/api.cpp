@@ -193,7 +193,9 @@ size_t batch_chunks(poisson_batch_t B, double budget_mb, std::vector<int> &chunk
 // compiled for pass k of plan P.  The conv pass has no tile width.
 bool schedule_valid(poisson_plan_t P, int k, int sched) {
   if (sched < 0 || sched >= psn::kSchedules) return false;
-  if (k == psn::KIND_CONV) return (sched & 3) == 0;
+  if (k == psn::KIND_CONV)
+    return (sched & 3) == 0 && (!(sched & psn::kPlaneBit) || psn::plane_available(P->g, P->precision));
+  if (sched & psn::kPlaneBit) return false;
   return psn::pass_tile_lines(P->g.pass[k], sched, P->precision) > 0;
 }
 
@@ -425,7 +427,20 @@ int enqueue_passes(poisson_plan_t P, int count, const float *const *rho, float *
   char *a2 = base + size_t(count) * g.a1_bytes;
   const int p = g.order[0], q = g.order[1], r = g.order[2];
   const float2 *tws[5] = {P->tw[p], P->tw[q], P->tw[r], P->tw[q], P->tw[p]};
+  // small grids: passes 1-3 as one plane kernel (schedule bit of pass 2)
+  const bool plane = (g.pass[2].tile_sel & psn::kPlaneBit) && first <= 1 && last >= 3 &&
+                     psn::plane_available(g, P->precision);
   for (int k = first; k <= last; ++k) {
+    if (plane && k >= 1 && k <= 3) {
+      if (k == 1) {
+        psn::PassIO io;
+        io.count = count;
+        for (int j = 0; j < count; ++j) io.out[j] = a1 + size_t(j) * g.a1_bytes;
+        hipError_t e = psn::launch_plane(g, io, P->tw[q], P->tw[r], P->kf32, s);
+        if (e != hipSuccess) return hip_fail(e, "plane launch");
+      }
+      continue;
+    }
     psn::PassIO io;
     io.count = count;
     io.conv_stride = (long long)(g.a2_bytes / sizeof(float2));
@@ -654,6 +669,22 @@ int poisson_plan_set_schedule(poisson_plan_t P, const int tile_sel[5]) {
                       std::to_string(k) + " of this plan");
   }
   for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = tile_sel[k];
+  return POISSON_OK;
+}
+
+int poisson_batch_set_schedule(poisson_batch_t B, const int tile_sel[5]) {
+  if (!B || !tile_sel) return fail(POISSON_E_ARG, "NULL argument");
+  for (size_t u = 0; u < B->plans.size(); ++u)
+    for (int k = 0; k < 5; ++k) {
+      if (tile_sel[k] < 0 || tile_sel[k] >= psn::kSchedules)
+        return fail(POISSON_E_ARG, "schedule out of range");
+      if (!schedule_valid(B->plans[u], k, tile_sel[k]))
+        return fail(POISSON_E_UNSUPPORTED,
+                    "schedule " + std::to_string(tile_sel[k]) + " is not compiled for pass " +
+                        std::to_string(k) + " of distinct problem " + std::to_string(u));
+    }
+  for (auto *P : B->plans)
+    for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = tile_sel[k];
   return POISSON_OK;
 }
 

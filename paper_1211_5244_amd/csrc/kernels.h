@@ -31,12 +31,23 @@ hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const 
 
 // Pass schedules (P.tile_sel = 0..kSchedules-1): bits 0-1 select the tile
 // width of a tiled pass (kTileSchedules choices; the conv pass has none),
-// bit 2 the XCD-blocked workgroup order.  pass_tile_lines gives the complex
-// lines per workgroup tile of schedule `sched` for pass P in `mode`, or 0
-// where its tile width is not compiled (it then runs as width 0).
+// bit 2 the XCD-blocked workgroup order, and bit 3 (conv pass only) runs
+// passes 1-3 as the small-grid plane kernel.  pass_tile_lines gives the
+// complex lines per workgroup tile of schedule `sched` for pass P in
+// `mode`, or 0 where its tile width is not compiled (it then runs as width 0).
 constexpr int kTileSchedules = 4;
-constexpr int kSchedules = 8;
+constexpr int kSchedules = 16;
+constexpr int kPlaneBit = 8;
 int pass_tile_lines(const Pass &P, int sched, int mode);
+
+// Small grids: passes 1-3 (forward q, conv r, inverse q) as one launch that
+// keeps each k_p plane in LDS.  plane_available tells whether geometry g has
+// a compiled plane kernel in `mode`; launch_plane runs it on the A1 arrays
+// io.out[j] in place (A1 doubles as A4), with the q and r twiddle tables and
+// the float32 K^F of the pass order.
+bool plane_available(const Geometry &g, int mode);
+hipError_t launch_plane(const Geometry &g, const PassIO &io, const float2 *twq, const float2 *twr,
+                        const float *kf, hipStream_t stream);
 
 // float64 K^F octant of the default Green's function (layout of the C ABI:
 // k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.

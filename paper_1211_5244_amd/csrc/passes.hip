@@ -816,6 +816,176 @@ hipError_t launch_for_mode(const Pass &P, const PassIO &io, const float2 *tw, co
   return hipErrorInvalidValue;
 }
 
+#if defined(PSN_PLANE_ONLY)
+// ------------------------------------------------------- small-grid plane
+// P2, P3 and P4 for one k_p plane at a time, with the plane held in LDS:
+// for a small grid the plane after the q transform (S_q x N_r complex) fits,
+// so the three passes become one launch and the intermediate A2 never
+// reaches HBM.  Phase A transforms the N_r q-lines of the plane from A1 into
+// the LDS plane, phase B runs the conv along r on its S_q rows in place, and
+// phase C transforms the q-lines back into A1 (which doubles as A4: every
+// plane reads all its elements before it writes any, and planes are
+// disjoint).  Each line's arithmetic is that of the three separate passes.
+struct PlaneParams {
+  float2 *data[kMaxBatch];  // A1 of each solve: read in phase A, overwritten in phase C
+  const float2 *twq, *twr;
+  const float *kf;          // [k_p][k_q'][k_r'] float32, 1/(S1 S2 S3) folded in
+  int s_r, s_p;             // A1 element strides along r and p (q-lines are contiguous)
+  int H;                    // planes per solve
+  int kq_half;              // S_q/2 + 1
+  int nplanes;              // H * solves
+};
+
+template <int LQ, int LR, bool PADQ, bool PADR> struct PlaneGeo {
+  static constexpr int EQ = Shape<LQ>::E, TQ = LQ / EQ, LPWQ = 64 / TQ;
+  static constexpr int ER = Shape<LR>::E, TR = LR / ER, LPWR = 64 / TR;
+  static constexpr int NQ = PADQ ? LQ / 2 : LQ, NR = PADR ? LR / 2 : LR;
+  static constexpr int PLD = NR + 1;  // plane row stride (float2), padded
+  static constexpr int XQ = LPWQ * line_lds_slots<LQ>(), XR = LPWR * line_lds_slots<LR>();
+  static constexpr int XW = XQ > XR ? XQ : XR;  // exchange slots per wavefront
+  static constexpr int NW = (LQ * PLD + 8 * XW) * 8 <= 150 * 1024 ? 8 : 4;
+  static constexpr int LDS_F2 = LQ * PLD + NW * XW;
+};
+
+template <int LQ, int LR, bool PADQ, bool PADR>
+__global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane_kernel(PlaneParams a) {
+  using C = PlaneGeo<LQ, LR, PADQ, PADR>;
+  constexpr int EQ = C::EQ, TQ = C::TQ, LPWQ = C::LPWQ, ER = C::ER, TR = C::TR, LPWR = C::LPWR;
+  constexpr int NR = C::NR, PLD = C::PLD, NW = C::NW, KR = LR / 2 + 1;
+  __shared__ float2 smem[C::LDS_F2];
+  float2 *plane = smem;
+  float2 *xbase = smem + LQ * PLD;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int gq = lane / TQ, tq = lane % TQ, gr = lane / TR, tr = lane % TR;
+  float2 *xq = xbase + wave * C::XW + gq * line_lds_slots<LQ>();
+  float2 *xr = xbase + wave * C::XW + gr * line_lds_slots<LR>();
+
+  LineEngine<LQ, MODE_FP32> engq;
+  engq.init(a.twq, lane);
+  LineEngine<LR, MODE_FP32> engr;
+  engr.init(a.twr, lane);
+
+  for (int pl = blockIdx.x; pl < a.nplanes; pl += gridDim.x) {
+    const int solve = pl / a.H, kp = pl % a.H;
+    float2 *base = a.data[solve] + kp * a.s_p;
+    // A: forward along q of the N_r lines (zero-padded half never loaded)
+    for (int r0 = 0; r0 < NR; r0 += NW * LPWQ) {
+      const int r = r0 + wave * LPWQ + gq;
+      const bool ok = r < NR;
+      const float2 *line = base + (ok ? r : 0) * a.s_r;
+      float2 v[EQ];
+#pragma unroll
+      for (int i = 0; i < EQ; ++i)
+        v[i] = ((!PADQ || i < EQ / 2) && ok) ? line[tq + TQ * i] : make_float2(0.f, 0.f);
+      engq.template run<false, PADQ>(v, xq, xq, lane);
+      if (ok) {
+#pragma unroll
+        for (int i = 0; i < EQ; ++i) plane[(tq + TQ * i) * PLD + r] = v[i];
+      }
+    }
+    __syncthreads();
+    // B: along r: forward, times K^F (even in k_q: row min(k_q, S_q - k_q)),
+    // inverse, crop; in place in the plane
+    for (int q0 = 0; q0 < LQ; q0 += NW * LPWR) {
+      const int kq = q0 + wave * LPWR + gr;
+      const bool ok = kq < LQ;
+      const int kqf = ok ? (kq <= LQ / 2 ? kq : LQ - kq) : 0;
+      const float *krow = a.kf + (kp * a.kq_half + kqf) * KR;
+      float2 *row = plane + (ok ? kq : 0) * PLD;
+      float2 v[ER];
+#pragma unroll
+      for (int i = 0; i < ER; ++i)
+        v[i] = (!PADR || i < ER / 2) ? row[tr + TR * i] : make_float2(0.f, 0.f);
+      engr.template run<false, PADR>(v, xr, xr, lane);
+#pragma unroll
+      for (int i = 0; i < ER; ++i) {
+        const float kv = i < ER / 2 ? krow[tr + TR * i] : krow[LR - tr - TR * i];
+        v[i] = make_float2(v[i].x * kv, v[i].y * kv);
+      }
+      engr.template run<true, false, PADR>(v, xr, xr, lane);
+      if (ok) {
+#pragma unroll
+        for (int i = 0; i < ER; ++i)
+          if (!PADR || i < ER / 2) row[tr + TR * i] = v[i];
+      }
+    }
+    __syncthreads();
+    // C: inverse along q, crop, back into A1
+    for (int r0 = 0; r0 < NR; r0 += NW * LPWQ) {
+      const int r = r0 + wave * LPWQ + gq;
+      const bool ok = r < NR;
+      float2 v[EQ];
+#pragma unroll
+      for (int i = 0; i < EQ; ++i) v[i] = plane[(tq + TQ * i) * PLD + (ok ? r : 0)];
+      engq.template run<true, false, PADQ>(v, xq, xq, lane);
+      if (ok) {
+        float2 *line = base + r * a.s_r;
+#pragma unroll
+        for (int i = 0; i < EQ; ++i)
+          if (!PADQ || i < EQ / 2) st_stream(&line[tq + TQ * i], v[i]);
+      }
+    }
+    __syncthreads();  // the plane is free for the next one
+  }
+}
+
+namespace {
+template <int LQ, int LR, bool PADQ, bool PADR>
+hipError_t launch_plane_t(const PlaneParams &a, hipStream_t s) {
+  auto k = plane_kernel<LQ, LR, PADQ, PADR>;
+  constexpr int NT = PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64;
+  const int grid = persistent_grid(k, NT, a.nplanes);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+// the compiled (L_q, L_r, padded q, padded r) combinations: cubic free,
+// wire and periodic grids and surface grids (q periodic, r free) up to 64
+#define PSN_PLANE_CASES(X)                                                      \
+  X(32, 32, false, false) X(48, 48, false, false) X(64, 64, false, false)       \
+  X(64, 64, true, true) X(96, 96, true, true) X(128, 128, true, true)          \
+  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)
+}  // namespace
+
+bool plane_available(const Geometry &g, int mode) {
+  if (mode != MODE_FP32) return false;
+  const Pass &P2 = g.pass[1], &P4 = g.pass[3];
+  if (P2.in_s[0] != 1 || P4.out_s[0] != 1) return false;  // q-lines contiguous in A1
+  const int LQ = P2.L, LR = g.pass[2].L;
+  const bool pq = P2.pad, pr = g.pass[2].pad;
+#define PSN_X(a, b, c, d) if (LQ == a && LR == b && pq == c && pr == d) return true;
+  PSN_PLANE_CASES(PSN_X)
+#undef PSN_X
+  return false;
+}
+
+hipError_t launch_plane(const Geometry &g, const PassIO &io, const float2 *twq, const float2 *twr,
+                        const float *kf, hipStream_t s) {
+  if (io.count < 1 || io.count > kMaxBatch || !plane_available(g, MODE_FP32))
+    return hipErrorInvalidValue;
+  const Pass &P2 = g.pass[1];
+  PlaneParams a;
+  for (int j = 0; j < kMaxBatch; ++j) a.data[j] = j < io.count ? static_cast<float2 *>(io.out[j]) : nullptr;
+  a.twq = twq;
+  a.twr = twr;
+  a.kf = kf;
+  a.s_r = int(P2.in_s[1]);
+  a.s_p = int(P2.in_s[2]);
+  a.H = P2.ext_batch;
+  a.kq_half = P2.L / 2 + 1;
+  a.nplanes = a.H * io.count;
+  const int LQ = P2.L, LR = g.pass[2].L;
+  const bool pq = P2.pad, pr = g.pass[2].pad;
+#define PSN_X(a_, b_, c_, d_) \
+  if (LQ == a_ && LR == b_ && pq == c_ && pr == d_) return launch_plane_t<a_, b_, c_, d_>(a, s);
+  PSN_PLANE_CASES(PSN_X)
+#undef PSN_X
+  return hipErrorInvalidValue;
+}
+#endif  // PSN_PLANE_ONLY
+
 #if defined(PSN_ONLY_LENGTH) && defined(PSN_ONLY_MODE)
 template hipError_t launch_for_mode<PSN_ONLY_LENGTH, PSN_ONLY_MODE>(const Pass &, const PassIO &,
                                                                     const float2 *, const float *,

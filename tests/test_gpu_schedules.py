@@ -1,10 +1,11 @@
 """GPU: pass schedules (tile width, XCD workgroup order) and the autotuner.
 
-A schedule only changes which lines a workgroup stages together and where
-it runs, so every compiled schedule must give results bitwise equal to
-schedule 0 (whose
-parity against the oracle the parity tests establish), on regular and ragged
-tiles.  The autotuner must leave a valid schedule and equal results.
+Tile widths and workgroup orders only change which lines a workgroup stages
+together and where it runs, so each must give results bitwise equal to
+schedule 0 (whose parity against the oracle the parity tests establish), on
+regular and ragged tiles.  The small-grid plane kernel (bit 3 of pass 2)
+must agree to float32 rounding and meet the oracle bar.  The autotuner must
+leave a valid schedule and equal results.
 """
 
 import numpy as np
@@ -57,15 +58,17 @@ CASES = [((256, 256, 256), 7), ((24, 48, 12), 7), ((48, 24, 64), 3), ((12, 48, 2
 
 
 @pytest.mark.parametrize("n,bc", CASES)
-def test_every_tile_schedule_is_bitwise_equal(torch_dev, n, bc):
+def test_every_schedule_keeps_results(torch_dev, n, bc):
     torch = torch_dev
     r = _rho(torch, n, bc, seed=700 + bc)
     plan = P.Plan(n, bc, H)
     ref = plan.solve(r).clone()
     compiled = _compiled(plan)
     print(f"{n} bc={bc}: compiled schedules per pass {compiled}", flush=True)
-    assert compiled[2] == [0, 4]  # the fused conv pass: no tile width, both orders
+    # the fused conv pass: no tile width, both orders, maybe the plane kernel
+    assert set(compiled[2]) in ({0, 4}, {0, 4, 8, 12})
     assert all(0 in c and 4 in c for c in compiled)  # the XCD order works everywhere
+    assert not any(sel & P.PLANE_BIT for k in (0, 1, 3, 4) for sel in compiled[k])
     # one pass at a time, then all passes together
     trials = []
     for k in range(5):
@@ -74,7 +77,8 @@ def test_every_tile_schedule_is_bitwise_equal(torch_dev, n, bc):
             sel[k] = ts
             trials.append(sel)
     for ts in range(1, P.TILE_SCHEDULES):  # every pass on schedule ts where compiled
-        trials.append([ts if ts in c else 0 for c in compiled])
+        if any(ts in c for c in compiled):
+            trials.append([ts if ts in c else 0 for c in compiled])
     for sel in trials:
         plan.set_schedule(sel)
         got_sel, lines = plan.schedule
@@ -82,7 +86,88 @@ def test_every_tile_schedule_is_bitwise_equal(torch_dev, n, bc):
         assert lines[2] == 0 and all(lines[k] > 0 for k in (0, 1, 3, 4))
         V = plan.solve(r)
         torch.cuda.synchronize()
-        assert torch.equal(V, ref), (n, bc, sel)
+        _assert_same_solve(V, ref, sel[2] & P.PLANE_BIT)
+
+
+# every compiled plane-kernel geometry: periodic, free, wire and surface cubes
+PLANE_CASES = [((32, 32, 32), 0), ((48, 48, 48), 0), ((64, 64, 64), 0), ((32, 32, 32), 7),
+               ((32, 32, 32), 3), ((48, 48, 48), 7), ((64, 64, 64), 7), ((32, 32, 32), 2),
+               ((48, 48, 48), 2), ((64, 64, 64), 2)]
+
+
+@pytest.mark.parametrize("n,bc", PLANE_CASES)
+def test_plane_kernel_matches_three_passes(torch_dev, n, bc):
+    """Passes 1-3 as one LDS-resident plane kernel (schedule bit 3 of pass 2)
+    against the three separate passes, and against the oracle; single solves
+    and a batch chunk of three.
+
+    The plane kernel evaluates the same butterflies as the separate passes,
+    but compiled inside one kernel the compiler orders and contracts a few
+    float32 operations differently, so results agree to float32 rounding
+    (relative L2 below 2e-7, measured 3e-8 to 9e-8) rather than bitwise.
+    Its own accuracy against the oracle must meet the float32 bar.  Between
+    two plane-kernel runs (XCD order on or off, single or batched) results
+    are bitwise equal: only the workgroup order differs there."""
+    torch = torch_dev
+    r = _rho(torch, n, bc, seed=900 + bc)
+    plan = P.Plan(n, bc, H)
+    ref = plan.solve(r).clone()
+    plan.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    V = plan.solve(r).clone()
+    torch.cuda.synchronize()
+    d = oracle.rel_l2(V.cpu().numpy(), ref.cpu().numpy().astype(np.float64))
+    assert d <= 2e-7, (n, bc, d)
+    err = oracle.rel_l2(V.cpu().numpy(), oracle.solve(r.cpu().numpy().astype(np.float64), bc, H))
+    assert err <= 1e-6
+    plan.set_schedule([0, 0, P.PLANE_BIT | 4, 0, 0])  # with the XCD order bit too
+    V2 = plan.solve(r)
+    torch.cuda.synchronize()
+    assert torch.equal(V2, V)
+    # batches: one plane-kernel launch covers every solve of a chunk, each
+    # solve bitwise equal to its single plane-kernel solve
+    rhos = [_rho(torch, n, bc, seed=910 + i) for i in range(3)]
+    B = P.Batch([n] * 3, [bc] * 3, [H] * 3)
+    B.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    Vs = [torch.empty_like(x) for x in rhos]
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    plan.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    for x, v in zip(rhos, Vs):
+        assert torch.equal(plan.solve(x), v)
+
+
+def test_batch_schedule_applies_to_every_problem(torch_dev):
+    """poisson_batch_set_schedule: all distinct problems or none."""
+    torch = torch_dev
+    cases = [((32, 32, 32), 7), ((48, 48, 48), 0), ((24, 48, 12), 7)]  # the last has no plane kernel
+    rhos = [_rho(torch, n, bc, seed=950 + i) for i, (n, bc) in enumerate(cases)]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * 3)
+    ref = [torch.empty_like(x) for x in rhos]
+    B.solve(rhos, ref)
+    with pytest.raises(P.PoissonError) as e:
+        B.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
+    with pytest.raises(P.PoissonError) as e:
+        B.set_schedule([0, 0, 0, P.TILE_SCHEDULES, 0])
+    assert e.value.code == P._lib.POISSON_E_ARG
+    Vs = [torch.empty_like(x) for x in rhos]
+    B.solve(rhos, Vs)  # unchanged after the rejected calls
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(Vs, ref))
+    B.set_schedule([4, 4, 4, 4, 4])  # XCD order: compiled everywhere, bitwise equal
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(Vs, ref))
+
+
+def _assert_same_solve(V, ref, plane):
+    """Bitwise equal, or with the plane kernel in play equal to float32
+    rounding (the bit-3 bound of test_plane_kernel_matches_three_passes)."""
+    if not plane:
+        assert (V == ref).all()
+        return
+    d = oracle.rel_l2(V.cpu().numpy(), ref.cpu().numpy().astype(np.float64))
+    assert d <= 2e-7, d
 
 
 def test_schedule_rejects_bad_values(torch_dev):
@@ -115,7 +200,7 @@ def test_tune_keeps_results(torch_dev, n, bc):
     assert all(np.isfinite(ms)) and all(x > 0 for x in ms)
     V = plan.solve(r)
     torch.cuda.synchronize()
-    assert torch.equal(V, ref)
+    _assert_same_solve(V, ref, sel[2] & P.PLANE_BIT)
     if n == (64, 96, 48):
         err = oracle.rel_l2(V.cpu().numpy(), oracle.solve(r.cpu().numpy().astype(np.float64), bc, H))
         assert err <= 1e-6
@@ -138,4 +223,5 @@ def test_batch_tune_keeps_results(torch_dev):
     B.solve(rhos, Vs)
     torch.cuda.synchronize()
     for i in range(len(cases)):
-        assert torch.equal(Vs[i], ref[i]), (i, cases[i])
+        # the tuner may pick the plane kernel for some problems
+        _assert_same_solve(Vs[i], ref[i], True)
