@@ -243,17 +243,23 @@ int poisson_plan_set_schedule(poisson_plan_t plan, const int tile_sel[5]);
  * changes). */
 int poisson_batch_set_schedule(poisson_batch_t batch, const int tile_sel[5]);
 
+/* The five schedules that solve `index` (creation order) runs with: those
+ * of its distinct problem.  POISSON_E_ARG if index is outside 0..count-1. */
+int poisson_batch_get_schedule(poisson_batch_t batch, int index, int tile_sel[5]);
+
 /* Current schedules and, per pass, the complex lines per tile they give
  * (0 for pass 2).  Either pointer may be NULL. */
 int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lines[5]);
 
-/* Autotuner: coordinate descent over the five passes.  For each pass, every
- * compiled schedule is timed as whole solves on this device (at least reps
- * solves and about 2 ms per round after a warm-up, best of two rounds,
- * hipEvents on `stream`), so a candidate is charged for what it leaves in
- * the caches for the next pass; it replaces the current choice only if the
- * solve gets at least 1% faster, and the final schedule is kept only if it
- * still beats the starting one when both are timed again.  Runs solves on
+/* Autotuner: coordinate descent over the five passes, pass 2 first (its
+ * bit 3 decides whether passes 1 and 3 run) and once more at the end.  For
+ * each pass, every compiled schedule is timed as whole solves on this
+ * device (at least reps solves and about 2 ms per round after a warm-up,
+ * best of two rounds, hipEvents on `stream`), so a candidate is charged for
+ * what it leaves in the caches for the next pass; it replaces the current
+ * choice only if the solve gets at least 1% faster, and the final schedule
+ * is kept only if it still beats the starting one when both are timed
+ * again.  Runs solves on
  * rho_dev and V_dev: V_dev (and the workspace) receive scratch values.
  * pass_ms (may be NULL) receives the chosen schedule's per-pass times.
  * reps <= 0 means 10.  Needs K^F and a workspace; synchronous. */

@@ -26,6 +26,7 @@ from ._lib import (  # noqa: F401
     poisson_batch_create,
     poisson_batch_destroy,
     poisson_batch_kernel_build,
+    poisson_batch_get_schedule,
     poisson_batch_set_schedule,
     poisson_batch_solve,
     poisson_batch_tune,
@@ -164,6 +165,10 @@ class Batch:
     def set_schedule(self, tile_sel):
         """The same five pass schedules for every distinct problem."""
         poisson_batch_set_schedule(self.handle, tile_sel)
+
+    def schedule(self, index):
+        """The five pass schedules solve `index` runs with."""
+        return poisson_batch_get_schedule(self.handle, index)
 
     def tune(self, rho_list, V_list, reps=0, stream=None):
         """Autotune tile schedules and the per-launch budget (V receives

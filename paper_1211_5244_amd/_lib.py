@@ -34,9 +34,8 @@ EXPORTED = (
     "poisson_solve_passes", "poisson_solve_host", "poisson_solve_host_many",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
-    "poisson_batch_set_schedule", "poisson_plan_get_schedule", "poisson_plan_tune",
-    "poisson_batch_tune", "poisson_rel_l2",
-    "poisson_last_error",
+    "poisson_batch_set_schedule", "poisson_batch_get_schedule", "poisson_plan_get_schedule",
+    "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2", "poisson_last_error",
 )
 
 # schedules per pass (poisson_plan_set_schedule): tile width in bits 0-1,
@@ -97,6 +96,7 @@ def load_library(path=None):
         "poisson_batch_destroy": (_i, [_vp]),
         "poisson_plan_set_schedule": (_i, [_vp, ctypes.POINTER(_i)]),
         "poisson_batch_set_schedule": (_i, [_vp, ctypes.POINTER(_i)]),
+        "poisson_batch_get_schedule": (_i, [_vp, _i, ctypes.POINTER(_i)]),
         "poisson_plan_get_schedule": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "poisson_plan_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
         "poisson_batch_tune": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
@@ -281,6 +281,12 @@ def poisson_plan_set_schedule(plan, tile_sel):
 def poisson_batch_set_schedule(batch, tile_sel):
     arr = (_i * 5)(*[int(x) for x in tile_sel])
     _check(load_library().poisson_batch_set_schedule(batch, arr))
+
+
+def poisson_batch_get_schedule(batch, index):
+    sel = (_i * 5)()
+    _check(load_library().poisson_batch_get_schedule(batch, int(index), sel))
+    return tuple(sel)
 
 
 def poisson_plan_get_schedule(plan):

@@ -688,6 +688,15 @@ int poisson_batch_set_schedule(poisson_batch_t B, const int tile_sel[5]) {
   return POISSON_OK;
 }
 
+int poisson_batch_get_schedule(poisson_batch_t B, int index, int tile_sel[5]) {
+  if (!B || !tile_sel) return fail(POISSON_E_ARG, "NULL argument");
+  if (index < 0 || index >= int(B->which.size()))
+    return fail(POISSON_E_ARG, "solve index " + std::to_string(index) + " out of range");
+  const poisson_plan_t P = B->plans[B->which[index]];
+  for (int k = 0; k < 5; ++k) tile_sel[k] = P->g.pass[k].tile_sel;
+  return POISSON_OK;
+}
+
 int poisson_plan_get_schedule(poisson_plan_t P, int tile_sel[5], int tile_lines[5]) {
   if (!P) return fail(POISSON_E_ARG, "plan is NULL");
   for (int k = 0; k < 5; ++k) {
@@ -732,7 +741,8 @@ template <typename F> int time_enqueue(F &&enqueue, hipStream_t s, int reps, dou
 }
 
 // Picks each pass's schedule for `count` solves of plan P run together
-// (arrays rho/V, intermediates in ws) by coordinate descent over the passes:
+// (arrays rho/V, intermediates in ws) by coordinate descent over the passes
+// (pass 2 first and last):
 // a candidate is timed as whole solves, so that what one pass leaves in the
 // caches (or evicts) for the next is part of its cost; it replaces the
 // current choice only when the solve gets at least 1% faster.  pass_ms (may
@@ -756,7 +766,9 @@ int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float
   rc = time_enqueue(solve, s, reps, &best);
   if (rc) return restore(rc);
   const double start_ms = best;
-  for (int k = 0; k < 5; ++k) {
+  // pass 2 first and again last: its plane-kernel choice decides whether
+  // passes 1 and 3 run at all, and so which schedules of the others pay
+  for (int k : {2, 0, 1, 3, 4, 2}) {
     psn::Pass &pass = P->g.pass[k];
     const int keep = pass.tile_sel;
     int best_sel = keep;

@@ -128,6 +128,7 @@ def test_plane_kernel_matches_three_passes(torch_dev, n, bc):
     rhos = [_rho(torch, n, bc, seed=910 + i) for i in range(3)]
     B = P.Batch([n] * 3, [bc] * 3, [H] * 3)
     B.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    assert all(B.schedule(i) == (0, 0, P.PLANE_BIT, 0, 0) for i in range(3))
     Vs = [torch.empty_like(x) for x in rhos]
     B.solve(rhos, Vs)
     torch.cuda.synchronize()
@@ -150,11 +151,16 @@ def test_batch_schedule_applies_to_every_problem(torch_dev):
     with pytest.raises(P.PoissonError) as e:
         B.set_schedule([0, 0, 0, P.TILE_SCHEDULES, 0])
     assert e.value.code == P._lib.POISSON_E_ARG
+    assert all(B.schedule(i) == (0,) * 5 for i in range(3))
+    with pytest.raises(P.PoissonError) as e:
+        B.schedule(3)
+    assert e.value.code == P._lib.POISSON_E_ARG
     Vs = [torch.empty_like(x) for x in rhos]
     B.solve(rhos, Vs)  # unchanged after the rejected calls
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(Vs, ref))
     B.set_schedule([4, 4, 4, 4, 4])  # XCD order: compiled everywhere, bitwise equal
+    assert all(B.schedule(i) == (4,) * 5 for i in range(3))
     B.solve(rhos, Vs)
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(Vs, ref))
@@ -217,7 +223,8 @@ def test_batch_tune_keeps_results(torch_dev):
     B.solve(rhos, ref)
     scratch = [torch.empty_like(r) for r in rhos]
     mb = B.tune(rhos, scratch, reps=2)
-    print(f"batch tune: {mb} MiB per launch", flush=True)
+    print(f"batch tune: {mb} MiB per launch; schedules {sorted(set(B.schedule(i) for i in range(len(cases))))}",
+          flush=True)
     assert mb in (32.0, 64.0, 96.0, 128.0, 192.0, 256.0, 384.0, 512.0)
     Vs = [torch.empty_like(r) for r in rhos]
     B.solve(rhos, Vs)
