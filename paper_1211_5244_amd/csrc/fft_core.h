@@ -57,10 +57,23 @@ template <int L> constexpr int span(int s) {
   for (int u = 0; u < s; ++u) p *= Shape<L>::R[u];
   return p;
 }
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+// Lane t's butterfly b of stage s has twiddle index k = (t + T b) mod NS.
+// Butterflies b and b + P, P = NS / gcd(T, NS), differ by a multiple of
+// lcm(T, NS) and so share their twiddles: a lane holds only the first
+// min(B, P) butterflies' sets.
+template <int L> constexpr int tw_period(int s) {
+  const int ns = span<L>(s);
+  return ns / cgcd(kT<L>, ns);
+}
+template <int L> constexpr int tw_sets(int s) {
+  const int b = Shape<L>::E / Shape<L>::R[s], p = tw_period<L>(s);
+  return b < p ? b : p;
+}
 // register offset of stage s's twiddles (stage 0 has none)
 template <int L> constexpr int tw_offset(int s) {
   int o = 0;
-  for (int u = 1; u < s; ++u) o += (Shape<L>::E / Shape<L>::R[u]) * (Shape<L>::R[u] - 1);
+  for (int u = 1; u < s; ++u) o += tw_sets<L>(u) * (Shape<L>::R[u] - 1);
   return o;
 }
 template <int L> constexpr int tw_count() { return tw_offset<L>(Shape<L>::NR) > 0 ? tw_offset<L>(Shape<L>::NR) : 1; }
@@ -193,10 +206,10 @@ template <int L> struct Twiddles {
   }
   template <int S> __device__ __forceinline__ void load_stage(const float2 *__restrict__ tab, int t) {
     if constexpr (S < Shape<L>::NR) {
-      constexpr int E = Shape<L>::E, R = Shape<L>::R[S], B = E / R, NS = span<L>(S);
-      constexpr int T = kT<L>, STEP = L / (NS * R), OFF = tw_offset<L>(S);
+      constexpr int R = Shape<L>::R[S], NS = span<L>(S);
+      constexpr int T = kT<L>, STEP = L / (NS * R), OFF = tw_offset<L>(S), D = tw_sets<L>(S);
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
+      for (int b = 0; b < D; ++b) {
         const int k = (t + T * b) % NS;
 #pragma unroll
         for (int m = 1; m < R; ++m) w[OFF + b * (R - 1) + (m - 1)] = tab[k * m * STEP];
@@ -214,7 +227,7 @@ template <int L, int S, bool INV, bool ZHI = false>
 __device__ __forceinline__ void fft_stage(float2 (&v)[Shape<L>::E], const Twiddles<L> &tw,
                                           float2 *__restrict__ lds, int t) {
   constexpr int E = Shape<L>::E, R = Shape<L>::R[S], B = E / R, NS = span<L>(S), T = kT<L>;
-  constexpr int OFF = tw_offset<L>(S);
+  constexpr int OFF = tw_offset<L>(S), P = tw_period<L>(S);
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     float2 a[R];
@@ -222,7 +235,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[Shape<L>::E], const Twiddl
     for (int m = 0; m < R; ++m) a[m] = v[b + m * B];
     if constexpr (S > 0) {
 #pragma unroll
-      for (int m = 1; m < R; ++m) a[m] = cmul_tw<INV>(a[m], tw.w[OFF + b * (R - 1) + (m - 1)]);
+      for (int m = 1; m < R; ++m) a[m] = cmul_tw<INV>(a[m], tw.w[OFF + (b % P) * (R - 1) + (m - 1)]);
     }
     dft<R, INV, ZHI && S == 0>(a);
 #pragma unroll
