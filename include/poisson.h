@@ -259,7 +259,7 @@ int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lin
  * what it leaves in the caches for the next pass; it replaces the current
  * choice only if the solve gets at least 1% faster, and the final schedule
  * is kept only if it still beats the starting one when both are timed
- * again.  Runs solves on
+ * again (alternately, best of two each).  Runs solves on
  * rho_dev and V_dev: V_dev (and the workspace) receive scratch values.
  * pass_ms (may be NULL) receives the chosen schedule's per-pass times.
  * reps <= 0 means 10.  Needs K^F and a workspace; synchronous. */
