@@ -164,7 +164,11 @@ int poisson_solve(poisson_plan_t plan, const float *rho_dev, float *V_dev, void 
  * written by pass 0 and 3; A2 at the next multiple of 256 bytes,
  * H*S_q*N_r elements, r fastest, then q, then p, written by passes 1 and 2.
  * The conv pass multiplies by K^F/(S1 S2 S3); inverse transforms are
- * unnormalized. */
+ * unnormalized.  With the plane kernel selected (schedule bit 3 of pass 2),
+ * a range that covers passes 1..3 runs them as that one kernel, which
+ * writes A1 only (A2 keeps stale values); any other range runs them as
+ * separate passes, whose results agree with the plane kernel's to float32
+ * rounding. */
 int poisson_solve_passes(poisson_plan_t plan, const float *rho_dev, float *V_dev, int first,
                          int last, void *stream);
 
