@@ -962,8 +962,13 @@ bool plane_available(const Geometry &g, int mode) {
   if (mode != MODE_FP32) return false;
   const Pass &P2 = g.pass[1], &P4 = g.pass[3];
   if (P2.in_s[0] != 1 || P4.out_s[0] != 1) return false;  // q-lines contiguous in A1
+  // the kernel writes each q-line back where it read it (A4 = A1), one plane
+  // per p index with N_r lines
   const int LQ = P2.L, LR = g.pass[2].L;
   const bool pq = P2.pad, pr = g.pass[2].pad;
+  if (P4.out_s[1] != P2.in_s[1] || P4.out_s[2] != P2.in_s[2] || P4.ext_tile != P2.ext_tile ||
+      P4.ext_batch != P2.ext_batch || P2.ext_batch != g.H || P2.ext_tile != (pr ? LR / 2 : LR))
+    return false;
 #define PSN_X(a, b, c, d) if (LQ == a && LR == b && pq == c && pr == d) return true;
   PSN_PLANE_CASES(PSN_X)
 #undef PSN_X

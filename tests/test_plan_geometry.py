@@ -102,3 +102,62 @@ def test_forced_orders_stay_in_bounds(dump, order, bc):
     assert res is not None
     assert tuple(res[0][:3]) == order
     _check(n, bc, *res)
+
+
+# the (L_q, L_r, padded q, padded r) combinations the plane kernel is built for
+PLANE_BUILT = {(32, 32, 0, 0), (48, 48, 0, 0), (64, 64, 0, 0), (64, 64, 1, 1), (96, 96, 1, 1),
+               (128, 128, 1, 1), (32, 64, 0, 1), (48, 96, 0, 1), (64, 128, 0, 1)}
+
+
+def _plane_ok(g, passes):
+    """The plane kernel's preconditions, as the library checks them."""
+    H = g[3 + g[0]] // 2 + 1
+    p2, p3, p4 = passes[1], passes[2], passes[3]
+    LQ, LR, pq, pr = p2[2], p3[2], p2[15], p3[15]
+    return (p2[7] == 1 and p4[10] == 1 and p4[11] == p2[8] and p4[12] == p2[9]
+            and p4[5] == p2[5] and p4[6] == p2[6] and p2[6] == H
+            and p2[5] == (LR // 2 if pr else LR) and (LQ, LR, pq, pr) in PLANE_BUILT)
+
+
+@pytest.mark.parametrize("e", [32, 48, 64])
+@pytest.mark.parametrize("bc", [0, 2, 3, 7])
+def test_plane_kernel_indexing(dump, e, bc):
+    """The small-grid plane kernel's own addressing, on the CPU: plane kp of
+    solve j reads and rewrites A1 at kp*s_p + r*s_r + q (q < N_q, r < N_r)
+    and K^F row (kp, min(k_q, L_q - k_q)) up to k_r = L_r/2.  Where the
+    library enables it, those offsets must stay inside A1 and the K^F table
+    and be exactly the elements pass 1 reads and pass 3 writes."""
+    n = (e, e, e)
+    res = dump(n, bc)
+    assert res is not None
+    g, passes = res
+    if not _plane_ok(g, passes):
+        pytest.skip("no plane kernel for this geometry")
+    a1 = g[6]
+    p2, p3 = passes[1], passes[2]
+    LQ, LR, pq, pr = p2[2], p3[2], p2[15], p3[15]
+    NQ, NR = (LQ // 2 if pq else LQ), (LR // 2 if pr else LR)
+    s_r, s_p, H = p2[8], p2[9], p2[6]
+    kp = np.arange(H)[:, None, None]
+    r = np.arange(NR)[None, :, None]
+    q = np.arange(NQ)[None, None, :]
+    offs = (kp * s_p + r * s_r + q).ravel()
+    assert offs.min() >= 0 and offs.max() < a1
+    assert len(np.unique(offs)) == len(offs) == a1
+    reads = _offsets(p2[3], p2[5], p2[6], p2[7:10])
+    writes = _offsets(passes[3][4], passes[3][5], passes[3][6], passes[3][10:13])
+    assert set(offs.tolist()) == set(reads.tolist()) == set(writes.tolist())
+    kq_half, KR = LQ // 2 + 1, LR // 2 + 1
+    kq = np.arange(LQ)
+    kqf = np.minimum(kq, LQ - kq)
+    krow_max = ((H - 1) * kq_half + kqf.max()) * KR + LR // 2
+    assert kqf.max() < kq_half and krow_max < H * kq_half * KR
+
+
+def test_plane_cases_of_the_gpu_tests_are_enabled(dump):
+    """Every geometry the GPU plane-kernel test selects has the kernel."""
+    for n, bc in [((32, 32, 32), 0), ((48, 48, 48), 0), ((64, 64, 64), 0), ((32, 32, 32), 7),
+                  ((32, 32, 32), 3), ((48, 48, 48), 7), ((64, 64, 64), 7), ((32, 32, 32), 2),
+                  ((48, 48, 48), 2), ((64, 64, 64), 2)]:
+        g, passes = dump(n, bc)
+        assert _plane_ok(g, passes), (n, bc)
