@@ -392,6 +392,7 @@ def main():
         for prec, name in ((P.POISSON_SPLIT_FP16, "fp16x2"), (P.POISSON_SPLIT_BF16, "bf16x3")):
             sp = P.Plan(n, bc, H, precision=prec)
             Vs = torch.empty_like(r)
+            sp.tune(r, Vs, stream=stream)  # tuned, as the float32 plan
             for _ in range(3):
                 sp.solve(r, Vs, stream)
             torch.cuda.synchronize()
@@ -403,7 +404,7 @@ def main():
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) / args.steps
             out["split"][name] = {"ms_per_solve": t, "solves_per_s": 1000.0 / t,
-                                  "V": Vs.cpu().numpy()}
+                                  "tile_schedule": list(sp.schedule[0]), "V": Vs.cpu().numpy()}
             sp.close()
     if not args.no_batch:
         out["batch"] = {"workload": "batch512 (edges 32..128, 4 BC classes, 4 Gaussians)",

@@ -225,16 +225,17 @@ int poisson_batch_destroy(poisson_batch_t batch);
  *    instead of every eighth one.
  *  - bit 3, pass 2 only: run passes 1-3 as one kernel that holds each k_p
  *    plane in LDS (the intermediate A2 never reaches HBM).  Compiled for
- *    float32 and small grids: L_q = L_r in {32, 48, 64} periodic, {64, 96,
- *    128} free, and (L_q, L_r) = (32, 64), (48, 96), (64, 128) with only r
- *    free, where the q-lines are contiguous in A1.  The schedules of passes 1
- *    and 3 are then unused.
+ *    every precision and small grids: L_q = L_r in {32, 48, 64} periodic,
+ *    {64, 96, 128} free, and (L_q, L_r) = (32, 64), (48, 96), (64, 128)
+ *    with only r free, where the q-lines are contiguous in A1.  The
+ *    schedules of passes 1 and 3 are then unused.
  * Bits 0-2 change which lines a workgroup transforms together, where it
  * runs and how long its HBM row segments are, never a line's arithmetic:
  * results are bitwise identical under all of them.  Bit 3 computes the same
- * butterflies in one kernel, where the compiler may order and contract a few
- * float32 operations differently: results then agree with the separate
- * passes to float32 rounding (relative L2 about 1e-7), not bitwise. */
+ * butterflies in one kernel.  In float32 the compiler may order and contract
+ * a few operations differently there: results then agree with the separate
+ * passes to float32 rounding (relative L2 about 1e-7), not bitwise.  The
+ * split modes fix their rounding order and stay bitwise equal. */
 
 /* Set the five passes' schedules.  POISSON_E_ARG if one is outside 0..15,
  * POISSON_E_UNSUPPORTED if its tile width is not compiled for its pass

@@ -62,8 +62,10 @@ def build(jobs=None, verbose=False):
                           (f"-DPSN_ONLY_LENGTH={L}", f"-DPSN_ONLY_MODE={mode}", *extra)))
     tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, "passes_dispatch.o"),
                   ("-DPSN_DISPATCH_ONLY=1",)))
-    tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, "passes_plane.o"),
-                  ("-DPSN_PLANE_ONLY=1",)))
+    for mode in (0, 1, 2):  # the small-grid plane kernel, one object per precision
+        extra = ("-mllvm", "-amdgpu-mfma-vgpr-form=1") if mode else ()
+        tasks.append((os.path.join(CSRC, "passes.hip"), os.path.join(BUILD, f"passes_plane_{mode}.o"),
+                      ("-DPSN_PLANE_ONLY=1", f"-DPSN_ONLY_MODE={mode}", *extra)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda t: _compile(*t), tasks))
     tmp = LIB + ".tmp"

@@ -436,7 +436,7 @@ int enqueue_passes(poisson_plan_t P, int count, const float *const *rho, float *
         psn::PassIO io;
         io.count = count;
         for (int j = 0; j < count; ++j) io.out[j] = a1 + size_t(j) * g.a1_bytes;
-        hipError_t e = psn::launch_plane(g, io, P->tw[q], P->tw[r], P->kf32, s);
+        hipError_t e = psn::launch_plane(g, P->precision, io, P->tw[q], P->tw[r], P->kf32, s);
         if (e != hipSuccess) return hip_fail(e, "plane launch");
       }
       continue;

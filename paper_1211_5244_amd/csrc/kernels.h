@@ -46,8 +46,11 @@ int pass_tile_lines(const Pass &P, int sched, int mode);
 // io.out[j] in place (A1 doubles as A4), with the q and r twiddle tables and
 // the float32 K^F of the pass order.
 bool plane_available(const Geometry &g, int mode);
-hipError_t launch_plane(const Geometry &g, const PassIO &io, const float2 *twq, const float2 *twr,
-                        const float *kf, hipStream_t stream);
+hipError_t launch_plane(const Geometry &g, int mode, const PassIO &io, const float2 *twq,
+                        const float2 *twr, const float *kf, hipStream_t stream);
+template <int MODE>
+hipError_t launch_plane_for_mode(const Geometry &g, const PassIO &io, const float2 *twq,
+                                 const float2 *twr, const float *kf, hipStream_t stream);
 
 // float64 K^F octant of the default Green's function (layout of the C ABI:
 // k1 fastest), built in place in `kf64` using `tmp` (same size) as scratch.

@@ -120,6 +120,14 @@ template <int L> int tile_lines_of(const Pass &P, int ts) {
   return 0;
 }
 
+// The small-grid plane kernel's compiled (L_q, L_r, padded q, padded r)
+// combinations: periodic, free and wire cubes and surface grids (q
+// periodic, r free), lengths up to 128.
+#define PSN_PLANE_CASES(X)                                                      \
+  X(32, 32, false, false) X(48, 48, false, false) X(64, 64, false, false)       \
+  X(64, 64, true, true) X(96, 96, true, true) X(128, 128, true, true)          \
+  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)
+
 #if !defined(PSN_DISPATCH_ONLY)
 
 // One launch covers `nsolve` solves of identical geometry; the tile index
@@ -856,7 +864,7 @@ template <int LQ, int LR, bool PADQ, bool PADR> struct PlaneGeo {
   static constexpr int LDS_F2 = LQ * PLD + NW * XW;
 };
 
-template <int LQ, int LR, bool PADQ, bool PADR>
+template <int LQ, int LR, bool PADQ, bool PADR, int MODE>
 __global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane_kernel(PlaneParams a) {
   using C = PlaneGeo<LQ, LR, PADQ, PADR>;
   constexpr int EQ = C::EQ, TQ = C::TQ, LPWQ = C::LPWQ, ER = C::ER, TR = C::TR, LPWR = C::LPWR;
@@ -867,12 +875,15 @@ __global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int gq = lane / TQ, tq = lane % TQ, gr = lane / TR, tr = lane % TR;
-  float2 *xq = xbase + wave * C::XW + gq * line_lds_slots<LQ>();
-  float2 *xr = xbase + wave * C::XW + gr * line_lds_slots<LR>();
+  // this wavefront's line regions (the split engine works on all of them
+  // together) and this line group's own
+  float2 *xw = xbase + wave * C::XW;
+  float2 *xq = xw + gq * line_lds_slots<LQ>();
+  float2 *xr = xw + gr * line_lds_slots<LR>();
 
-  LineEngine<LQ, MODE_FP32> engq;
+  LineEngine<LQ, MODE> engq;
   engq.init(a.twq, lane);
-  LineEngine<LR, MODE_FP32> engr;
+  LineEngine<LR, MODE> engr;
   engr.init(a.twr, lane);
 
   for (int pl = blockIdx.x; pl < a.nplanes; pl += gridDim.x) {
@@ -887,7 +898,7 @@ __global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane
 #pragma unroll
       for (int i = 0; i < EQ; ++i)
         v[i] = ((!PADQ || i < EQ / 2) && ok) ? line[tq + TQ * i] : make_float2(0.f, 0.f);
-      engq.template run<false, PADQ>(v, xq, xq, lane);
+      engq.template run<false, PADQ>(v, xq, xw, lane);
       if (ok) {
 #pragma unroll
         for (int i = 0; i < EQ; ++i) plane[(tq + TQ * i) * PLD + r] = v[i];
@@ -906,13 +917,13 @@ __global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane
 #pragma unroll
       for (int i = 0; i < ER; ++i)
         v[i] = (!PADR || i < ER / 2) ? row[tr + TR * i] : make_float2(0.f, 0.f);
-      engr.template run<false, PADR>(v, xr, xr, lane);
+      engr.template run<false, PADR>(v, xr, xw, lane);
 #pragma unroll
       for (int i = 0; i < ER; ++i) {
         const float kv = i < ER / 2 ? krow[tr + TR * i] : krow[LR - tr - TR * i];
         v[i] = make_float2(v[i].x * kv, v[i].y * kv);
       }
-      engr.template run<true, false, PADR>(v, xr, xr, lane);
+      engr.template run<true, false, PADR>(v, xr, xw, lane);
       if (ok) {
 #pragma unroll
         for (int i = 0; i < ER; ++i)
@@ -927,7 +938,7 @@ __global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane
       float2 v[EQ];
 #pragma unroll
       for (int i = 0; i < EQ; ++i) v[i] = plane[(tq + TQ * i) * PLD + (ok ? r : 0)];
-      engq.template run<true, false, PADQ>(v, xq, xq, lane);
+      engq.template run<true, false, PADQ>(v, xq, xw, lane);
       if (ok) {
         float2 *line = base + r * a.s_r;
 #pragma unroll
@@ -940,45 +951,22 @@ __global__ __launch_bounds__((PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64)) void plane
 }
 
 namespace {
-template <int LQ, int LR, bool PADQ, bool PADR>
+template <int LQ, int LR, bool PADQ, bool PADR, int MODE>
 hipError_t launch_plane_t(const PlaneParams &a, hipStream_t s) {
-  auto k = plane_kernel<LQ, LR, PADQ, PADR>;
+  auto k = plane_kernel<LQ, LR, PADQ, PADR, MODE>;
   constexpr int NT = PlaneGeo<LQ, LR, PADQ, PADR>::NW * 64;
   const int grid = persistent_grid(k, NT, a.nplanes);
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(grid), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
-
-// the compiled (L_q, L_r, padded q, padded r) combinations: cubic free,
-// wire and periodic grids and surface grids (q periodic, r free) up to 64
-#define PSN_PLANE_CASES(X)                                                      \
-  X(32, 32, false, false) X(48, 48, false, false) X(64, 64, false, false)       \
-  X(64, 64, true, true) X(96, 96, true, true) X(128, 128, true, true)          \
-  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)
 }  // namespace
 
-bool plane_available(const Geometry &g, int mode) {
-  if (mode != MODE_FP32) return false;
-  const Pass &P2 = g.pass[1], &P4 = g.pass[3];
-  if (P2.in_s[0] != 1 || P4.out_s[0] != 1) return false;  // q-lines contiguous in A1
-  // the kernel writes each q-line back where it read it (A4 = A1), one plane
-  // per p index with N_r lines
-  const int LQ = P2.L, LR = g.pass[2].L;
-  const bool pq = P2.pad, pr = g.pass[2].pad;
-  if (P4.out_s[1] != P2.in_s[1] || P4.out_s[2] != P2.in_s[2] || P4.ext_tile != P2.ext_tile ||
-      P4.ext_batch != P2.ext_batch || P2.ext_batch != g.H || P2.ext_tile != (pr ? LR / 2 : LR))
-    return false;
-#define PSN_X(a, b, c, d) if (LQ == a && LR == b && pq == c && pr == d) return true;
-  PSN_PLANE_CASES(PSN_X)
-#undef PSN_X
-  return false;
-}
-
-hipError_t launch_plane(const Geometry &g, const PassIO &io, const float2 *twq, const float2 *twr,
-                        const float *kf, hipStream_t s) {
-  if (io.count < 1 || io.count > kMaxBatch || !plane_available(g, MODE_FP32))
-    return hipErrorInvalidValue;
+// launch_plane's per-precision half (each precision is its own object); the
+// caller has checked plane_available
+template <int MODE>
+hipError_t launch_plane_for_mode(const Geometry &g, const PassIO &io, const float2 *twq,
+                                 const float2 *twr, const float *kf, hipStream_t s) {
   const Pass &P2 = g.pass[1];
   PlaneParams a;
   for (int j = 0; j < kMaxBatch; ++j) a.data[j] = j < io.count ? static_cast<float2 *>(io.out[j]) : nullptr;
@@ -993,11 +981,14 @@ hipError_t launch_plane(const Geometry &g, const PassIO &io, const float2 *twq, 
   const int LQ = P2.L, LR = g.pass[2].L;
   const bool pq = P2.pad, pr = g.pass[2].pad;
 #define PSN_X(a_, b_, c_, d_) \
-  if (LQ == a_ && LR == b_ && pq == c_ && pr == d_) return launch_plane_t<a_, b_, c_, d_>(a, s);
+  if (LQ == a_ && LR == b_ && pq == c_ && pr == d_) return launch_plane_t<a_, b_, c_, d_, MODE>(a, s);
   PSN_PLANE_CASES(PSN_X)
 #undef PSN_X
   return hipErrorInvalidValue;
 }
+template hipError_t launch_plane_for_mode<PSN_ONLY_MODE>(const Geometry &, const PassIO &,
+                                                         const float2 *, const float2 *,
+                                                         const float *, hipStream_t);
 #endif  // PSN_PLANE_ONLY
 
 #if defined(PSN_ONLY_LENGTH) && defined(PSN_ONLY_MODE)
@@ -1046,6 +1037,31 @@ int pass_tile_lines(const Pass &P, int sched, int mode) {
 #undef PSN_CASE
   }
   return 0;
+}
+
+bool plane_available(const Geometry &g, int mode) {
+  if (mode < MODE_FP32 || mode > MODE_SPLIT_BF16) return false;
+  const Pass &P2 = g.pass[1], &P4 = g.pass[3];
+  if (P2.in_s[0] != 1 || P4.out_s[0] != 1) return false;  // q-lines contiguous in A1
+  // the kernel writes each q-line back where it read it (A4 = A1), one plane
+  // per p index with N_r lines
+  const int LQ = P2.L, LR = g.pass[2].L;
+  const bool pq = P2.pad, pr = g.pass[2].pad;
+  if (P4.out_s[1] != P2.in_s[1] || P4.out_s[2] != P2.in_s[2] || P4.ext_tile != P2.ext_tile ||
+      P4.ext_batch != P2.ext_batch || P2.ext_batch != g.H || P2.ext_tile != (pr ? LR / 2 : LR))
+    return false;
+#define PSN_X(a, b, c, d) if (LQ == a && LR == b && pq == c && pr == d) return true;
+  PSN_PLANE_CASES(PSN_X)
+#undef PSN_X
+  return false;
+}
+
+hipError_t launch_plane(const Geometry &g, int mode, const PassIO &io, const float2 *twq,
+                        const float2 *twr, const float *kf, hipStream_t s) {
+  if (io.count < 1 || io.count > kMaxBatch || !plane_available(g, mode)) return hipErrorInvalidValue;
+  if (mode == MODE_SPLIT_FP16) return launch_plane_for_mode<MODE_SPLIT_FP16>(g, io, twq, twr, kf, s);
+  if (mode == MODE_SPLIT_BF16) return launch_plane_for_mode<MODE_SPLIT_BF16>(g, io, twq, twr, kf, s);
+  return launch_plane_for_mode<MODE_FP32>(g, io, twq, twr, kf, s);
 }
 
 #endif  // PSN_DISPATCH_ONLY

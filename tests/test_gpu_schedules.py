@@ -137,6 +137,37 @@ def test_plane_kernel_matches_three_passes(torch_dev, n, bc):
         assert torch.equal(plan.solve(x), v)
 
 
+@pytest.mark.parametrize("precision", [P.POISSON_SPLIT_FP16, P.POISSON_SPLIT_BF16])
+@pytest.mark.parametrize("n,bc", [((32, 32, 32), 7), ((48, 48, 48), 0), ((64, 64, 64), 2),
+                                  ((32, 32, 32), 3), ((64, 64, 64), 7)])
+def test_split_plane_kernel_equals_three_passes(torch_dev, n, bc, precision):
+    """The plane kernel in the split modes.  The split line transform fixes
+    its rounding order (matrix-core products, twiddle products with a fixed
+    fused form), so unlike float32 the fused kernel gives results bitwise
+    equal to the separate passes; they must meet the oracle bar, single and
+    batched."""
+    torch = torch_dev
+    r = _rho(torch, n, bc, seed=960 + bc)
+    plan = P.Plan(n, bc, H, precision=precision)
+    ref = plan.solve(r).clone()
+    plan.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    V = plan.solve(r).clone()
+    torch.cuda.synchronize()
+    d = oracle.rel_l2(V.cpu().numpy(), ref.cpu().numpy().astype(np.float64))
+    err = oracle.rel_l2(V.cpu().numpy(), oracle.solve(r.cpu().numpy().astype(np.float64), bc, H))
+    print(f"{n} bc={bc} precision={precision}: plane vs passes {d:.2e}, vs oracle {err:.2e}", flush=True)
+    assert torch.equal(V, ref), d
+    assert err <= 1e-6, err
+    rhos = [_rho(torch, n, bc, seed=970 + i) for i in range(3)]
+    B = P.Batch([n] * 3, [bc] * 3, [H] * 3, precision=precision)
+    B.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    Vs = [torch.empty_like(x) for x in rhos]
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for x, v in zip(rhos, Vs):
+        assert torch.equal(plan.solve(x), v)
+
+
 def test_batch_schedule_applies_to_every_problem(torch_dev):
     """poisson_batch_set_schedule: all distinct problems or none."""
     torch = torch_dev
