@@ -860,7 +860,12 @@ template <int LQ, int LR, bool PADQ, bool PADR> struct PlaneGeo {
   static constexpr int PLD = NR + 1;  // plane row stride (float2), padded
   static constexpr int XQ = LPWQ * line_lds_slots<LQ>(), XR = LPWR * line_lds_slots<LR>();
   static constexpr int XW = XQ > XR ? XQ : XR;  // exchange slots per wavefront
-  static constexpr int NW = (LQ * PLD + 8 * XW) * 8 <= 150 * 1024 ? 8 : 4;
+  // wavefronts: enough for the larger phase (N_r q-lines, or L_q r-rows) in
+  // one round, at most 8, and 4 where 8 would not fit the LDS
+  static constexpr int NEED_A = (NR + LPWQ - 1) / LPWQ, NEED_B = (LQ + LPWR - 1) / LPWR;
+  static constexpr int NEED = NEED_A > NEED_B ? NEED_A : NEED_B;
+  static constexpr int NW8 = NEED < 8 ? NEED : 8;
+  static constexpr int NW = (LQ * PLD + NW8 * XW) * 8 <= 150 * 1024 ? NW8 : (NW8 < 4 ? NW8 : 4);
   static constexpr int LDS_F2 = LQ * PLD + NW * XW;
 };
 
