@@ -263,3 +263,35 @@ def test_batch_tune_keeps_results(torch_dev):
     for i in range(len(cases)):
         # the tuner may pick the plane kernel for some problems
         _assert_same_solve(Vs[i], ref[i], True)
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP32, P.POISSON_SPLIT_FP16])
+def test_plane_kernel_batch_in_a_graph(torch_dev, precision):
+    """A batch on the plane kernel captured in a HIP graph: every replay,
+    with eager work between replays, equals the eager batch bitwise."""
+    torch = torch_dev
+    cases = [((32, 32, 32), 7), ((48, 48, 48), 0), ((64, 64, 64), 2), ((32, 32, 32), 7)]
+    rhos = [_rho(torch, n, bc, seed=990 + i) for i, (n, bc) in enumerate(cases)]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases), precision=precision)
+    B.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    Vs = [torch.empty_like(r) for r in rhos]
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    eager = [v.clone() for v in Vs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in Vs:
+            v.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert torch.equal(Vs[i], eager[i]), (rep, i)
+        B.solve(rhos, Vs)  # eager work between replays
+        torch.cuda.synchronize()
