@@ -44,7 +44,8 @@ int pass_tile_lines(const Pass &P, int sched, int mode);
 // keeps each k_p plane in LDS.  plane_available tells whether geometry g has
 // a compiled plane kernel in `mode`; launch_plane runs it on the A1 arrays
 // io.out[j] in place (A1 doubles as A4), with the q and r twiddle tables and
-// the float32 K^F of the pass order.
+// the float32 K^F of the pass order.  launch_plane_for_mode is its
+// per-precision half (each precision compiled in its own object).
 bool plane_available(const Geometry &g, int mode);
 hipError_t launch_plane(const Geometry &g, int mode, const PassIO &io, const float2 *twq,
                         const float2 *twr, const float *kf, hipStream_t stream);
