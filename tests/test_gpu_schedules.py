@@ -295,3 +295,32 @@ def test_plane_kernel_batch_in_a_graph(torch_dev, precision):
             assert torch.equal(Vs[i], eager[i]), (rep, i)
         B.solve(rhos, Vs)  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_solve_passes_with_the_plane_bit(torch_dev):
+    """poisson_solve_passes with the plane kernel selected: a range over
+    passes 1-3 runs the plane kernel (equal to poisson_solve bitwise), any
+    other split of the passes runs them separately (equal to the solve
+    without the plane kernel bitwise)."""
+    torch = torch_dev
+    n, bc = (32, 32, 32), 7
+    r = _rho(torch, n, bc, seed=995)
+    plan = P.Plan(n, bc, H)
+    separate = plan.solve(r).clone()
+    plan.set_schedule([0, 0, P.PLANE_BIT, 0, 0])
+    fused = plan.solve(r).clone()
+    s = torch.cuda.current_stream()
+    V = torch.empty_like(r)
+    P.poisson_solve_passes(plan.handle, r, V, 0, 4, s)
+    torch.cuda.synchronize()
+    assert torch.equal(V, fused)
+    V.zero_()
+    P.poisson_solve_passes(plan.handle, r, V, 0, 3, s)
+    P.poisson_solve_passes(plan.handle, r, V, 4, 4, s)
+    torch.cuda.synchronize()
+    assert torch.equal(V, fused)
+    V.zero_()
+    for first, last in ((0, 1), (2, 4)):
+        P.poisson_solve_passes(plan.handle, r, V, first, last, s)
+    torch.cuda.synchronize()
+    assert torch.equal(V, separate)
