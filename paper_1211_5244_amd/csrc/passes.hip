@@ -120,14 +120,6 @@ template <int L> int tile_lines_of(const Pass &P, int ts) {
   return 0;
 }
 
-// The small-grid plane kernel's compiled (L_q, L_r, padded q, padded r)
-// combinations: periodic, free and wire cubes and surface grids (q
-// periodic, r free), lengths up to 128.
-#define PSN_PLANE_CASES(X)                                                      \
-  X(32, 32, false, false) X(48, 48, false, false) X(64, 64, false, false)       \
-  X(64, 64, true, true) X(96, 96, true, true) X(128, 128, true, true)          \
-  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)
-
 #if !defined(PSN_DISPATCH_ONLY)
 
 // One launch covers `nsolve` solves of identical geometry; the tile index
@@ -1046,19 +1038,7 @@ int pass_tile_lines(const Pass &P, int sched, int mode) {
 
 bool plane_available(const Geometry &g, int mode) {
   if (mode < MODE_FP32 || mode > MODE_SPLIT_BF16) return false;
-  const Pass &P2 = g.pass[1], &P4 = g.pass[3];
-  if (P2.in_s[0] != 1 || P4.out_s[0] != 1) return false;  // q-lines contiguous in A1
-  // the kernel writes each q-line back where it read it (A4 = A1), one plane
-  // per p index with N_r lines
-  const int LQ = P2.L, LR = g.pass[2].L;
-  const bool pq = P2.pad, pr = g.pass[2].pad;
-  if (P4.out_s[1] != P2.in_s[1] || P4.out_s[2] != P2.in_s[2] || P4.ext_tile != P2.ext_tile ||
-      P4.ext_batch != P2.ext_batch || P2.ext_batch != g.H || P2.ext_tile != (pr ? LR / 2 : LR))
-    return false;
-#define PSN_X(a, b, c, d) if (LQ == a && LR == b && pq == c && pr == d) return true;
-  PSN_PLANE_CASES(PSN_X)
-#undef PSN_X
-  return false;
+  return plane_geometry_ok(g);
 }
 
 hipError_t launch_plane(const Geometry &g, int mode, const PassIO &io, const float2 *twq,

@@ -36,6 +36,27 @@ double algorithmic_bytes(const int n[3], const int S[3], const int order[3]) {
          + 4.0 * H * (S[q] / 2 + 1) * (S[r] / 2 + 1);  // K^F octant, float32, once
 }
 
+bool plane_geometry_ok(const Geometry &g) {
+  const Pass &P2 = g.pass[1], &P4 = g.pass[3];
+  if (P2.in_s[0] != 1 || P4.out_s[0] != 1) return false;  // q-lines contiguous in A1
+  const int LQ = P2.L, LR = g.pass[2].L;
+  const bool pq = P2.pad, pr = g.pass[2].pad;
+  if (P4.out_s[1] != P2.in_s[1] || P4.out_s[2] != P2.in_s[2] || P4.ext_tile != P2.ext_tile ||
+      P4.ext_batch != P2.ext_batch || P2.ext_batch != g.H || P2.ext_tile != (pr ? LR / 2 : LR))
+    return false;
+#define PSN_X(a, b, c, d) if (LQ == a && LR == b && pq == c && pr == d) return true;
+  PSN_PLANE_CASES(PSN_X)
+#undef PSN_X
+  return false;
+}
+
+double algorithmic_bytes_plane(const Geometry &g) {
+  const int p = g.order[0], q = g.order[1], r = g.order[2];
+  const double H = g.S[p] / 2 + 1;
+  const double grid = double(g.n[0]) * g.n[1] * g.n[2];
+  return 8.0 * grid + 32.0 * H * g.n[q] * g.n[r] + 4.0 * H * (g.S[q] / 2 + 1) * (g.S[r] / 2 + 1);
+}
+
 namespace {
 
 // strides (elements) per physical axis for an array whose axes, fastest

@@ -58,4 +58,23 @@ int build_geometry(int n1, int n2, int n3, unsigned bc, Geometry &g, std::string
 // reading and writing its data once, plus the float32 K^F octant).
 double algorithmic_bytes(const int n[3], const int S[3], const int order[3]);
 
+// The small-grid plane kernel's compiled (L_q, L_r, padded q, padded r)
+// combinations: periodic, free and wire cubes and surface grids (q
+// periodic, r free), lengths up to 128.
+#define PSN_PLANE_CASES(X)                                                      \
+  X(32, 32, false, false) X(48, 48, false, false) X(64, 64, false, false)       \
+  X(64, 64, true, true) X(96, 96, true, true) X(128, 128, true, true)          \
+  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)
+
+// Whether geometry g can run passes 1-3 as the plane kernel: a compiled
+// (L_q, L_r) case whose q-lines are contiguous in A1 and are written back
+// where they were read (A4 = A1), one k_p plane of N_r lines per p index.
+bool plane_geometry_ok(const Geometry &g);
+
+// Minimum HBM bytes of one solve that runs passes 1-3 as the plane kernel:
+// the intermediate A2 stays in LDS, so only the density, A1 (written by
+// pass 0, read and rewritten by the plane kernel, read by pass 4), the
+// potential and the K^F octant move.
+double algorithmic_bytes_plane(const Geometry &g);
+
 }  // namespace psn

@@ -24,8 +24,8 @@ int main(int argc, char **argv) {
     std::printf("error %d %s\n", rc, err.c_str());
     return 0;
   }
-  std::printf("geometry %d %d %d %d %d %d %lld %lld\n", g.order[0], g.order[1], g.order[2], g.S[0],
-              g.S[1], g.S[2], g.a1_elems, g.a2_elems);
+  std::printf("geometry %d %d %d %d %d %d %lld %lld %d\n", g.order[0], g.order[1], g.order[2], g.S[0],
+              g.S[1], g.S[2], g.a1_elems, g.a2_elems, int(psn::plane_geometry_ok(g)));
   for (int k = 0; k < 5; ++k) {
     const psn::Pass &P = g.pass[k];
     std::printf("pass %d %d %d %d %d %d %d %lld %lld %lld %lld %lld %lld %d %d %d %d\n", k, P.kind,
