@@ -84,12 +84,20 @@ __host__ __device__ constexpr int lds_pad(int o) { return o + (o >> 4); }
 template <int L> constexpr int line_lds_slots() { return lds_pad(L - 1) + 1; }
 
 // --------------------------------------------------------------- complex ops
+// Rounding is fixed in the source: the compiler contracts nothing in this
+// file (fp contract off), and the products that should fuse are written as
+// fmaf.  A line's result then does not depend on which kernel inlines its
+// transform or where (the plane kernel and the separate passes, a batched
+// launch and a lone one, every tile schedule give identical bits).
+#pragma clang fp contract(off)
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-// a * w (forward) or a * conj(w) (inverse)
+// a * w (forward) or a * conj(w) (inverse): one product rounded, one fused
 template <bool INV> __device__ __forceinline__ float2 cmul_tw(float2 a, float2 w) {
-  if constexpr (!INV) return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
-  else return make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+  if constexpr (!INV)
+    return make_float2(__builtin_fmaf(a.x, w.x, -(a.y * w.y)), __builtin_fmaf(a.x, w.y, a.y * w.x));
+  else
+    return make_float2(__builtin_fmaf(a.x, w.x, a.y * w.y), __builtin_fmaf(a.y, w.x, -(a.x * w.y)));
 }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV> __device__ __forceinline__ float2 mul_mi(float2 a) {
@@ -117,12 +125,13 @@ template <bool INV> __device__ __forceinline__ void dft3(float2 *a) {
   constexpr float c = 0.86602540378443864676f;  // sqrt(3)/2
   float2 s = cadd(a[1], a[2]);
   float2 d = csub(a[1], a[2]);
-  float2 m = make_float2(a[0].x - 0.5f * s.x, a[0].y - 0.5f * s.y);
-  // forward: X1 = m - i c d, X2 = m + i c d
-  float2 icd = make_float2(-c * d.y, c * d.x);  // i c d
+  float2 m = make_float2(__builtin_fmaf(-0.5f, s.x, a[0].x), __builtin_fmaf(-0.5f, s.y, a[0].y));
+  // forward: X1 = m - i c d, X2 = m + i c d (i c d = (-c d.y, c d.x))
+  const float2 p = make_float2(__builtin_fmaf(c, d.y, m.x), __builtin_fmaf(-c, d.x, m.y));  // m - i c d
+  const float2 q = make_float2(__builtin_fmaf(-c, d.y, m.x), __builtin_fmaf(c, d.x, m.y));  // m + i c d
   a[0] = cadd(a[0], s);
-  if constexpr (!INV) { a[1] = csub(m, icd); a[2] = cadd(m, icd); }
-  else { a[1] = cadd(m, icd); a[2] = csub(m, icd); }
+  if constexpr (!INV) { a[1] = p; a[2] = q; }
+  else { a[1] = q; a[2] = p; }
 }
 
 template <bool INV, bool ZHI = false> __device__ __forceinline__ void dft4(float2 *a) {
