@@ -25,8 +25,14 @@ PASS_NAMES = ["p1_r2c", "p2_fwd", "p3_conv", "p4_inv", "p5_c2r"]
 H = 0.3
 
 
-def pass_bytes(n, info):
-    """Algorithmic HBM bytes of each pass (each array read and written once)."""
+PLANE_BIT = 8  # schedule bit of pass 2: passes 1-3 run as the small-grid plane kernel
+
+
+def pass_bytes(n, info, plane=False):
+    """Algorithmic HBM bytes of each launch (each array read and written
+    once).  Five passes, or with the plane kernel three launches: pass 0,
+    passes 1-3 (A1 read and rewritten, the K^F octant read; A2 stays in LDS)
+    and pass 4."""
     S = info["S"]
     p, q, r = info["axis_order"]
     Hc = S[p] // 2 + 1
@@ -34,7 +40,21 @@ def pass_bytes(n, info):
     a1 = 8 * Hc * n[q] * n[r]
     a2 = 8 * Hc * S[q] * n[r]
     kf = 4 * Hc * (S[q] // 2 + 1) * (S[r] // 2 + 1)
+    if plane:
+        return [4 * grid + a1, 2 * a1 + kf, a1 + 4 * grid]
     return [4 * grid + a1, a1 + a2, 2 * a2 + kf, a2 + a1, a1 + 4 * grid]
+
+
+def launches(tile_sel):
+    """(name, first pass, last pass) of each launch a solve runs with the
+    schedule tile_sel."""
+    if tile_sel[2] & PLANE_BIT:
+        return [("p1_r2c", 0, 0), ("p2_plane", 1, 3), ("p5_c2r", 4, 4)]
+    return [(PASS_NAMES[k], k, k) for k in range(5)]
+
+
+def solve_bytes(n, info, tile_sel):
+    return float(sum(pass_bytes(n, info, plane=bool(tile_sel[2] & PLANE_BIT))))
 
 
 def measured_traffic(kernel):
@@ -146,6 +166,7 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     t_loop = timed(loop)
     ref = [v.clone() for v in Vs]
     t_batch = timed(batched)
+    descr = {key: P.poisson_plan_describe(*key[0], key[1]) for key in plans}
 
     def max_rel_diff():  # largest relative L2 difference from the per-solve loop
         return max(float((a.double() - b.double()).norm() / a.double().norm()) for a, b in zip(ref, Vs))
@@ -173,12 +194,18 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     torch.cuda.synchronize()
     t_tuned_graph = timed(g2.replay)
     tuned_diff = max(tuned_diff, max_rel_diff())
-    out = {"solves": len(items), "alg_bytes": alg, "untuned_identical_to_loop": bool(same),
+    # the tuned batch's bytes follow the schedules it runs (the plane kernel
+    # keeps A2 in LDS)
+    alg_tuned = sum(solve_bytes(n, descr[(n, bc)], B.schedule(i)) for i, (n, bc, _) in enumerate(items))
+    out = {"solves": len(items), "alg_bytes": alg, "alg_bytes_tuned": alg_tuned,
+           "tuned_identical_to_loop": tuned_diff == 0.0,
+           "untuned_identical_to_loop": bool(same),
            "tuned_max_rel_l2_vs_loop": tuned_diff, "tuned_chunk_mb": chunk_mb}
     for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph),
                     ("batched_tuned", t_tuned), ("batched_tuned_graph", t_tuned_graph)):
+        a = alg_tuned if "tuned" in name else alg
         out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),
-                     "alg_gbs": alg / (t * 1e-3) / 1e9}
+                     "alg_gbs": a / (t * 1e-3) / 1e9}
     return out
 
 
@@ -332,26 +359,32 @@ def main():
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / args.steps
+    # accuracy of exactly the path timed above (whole solves, tuned schedule)
+    V_gpu = V.cpu().numpy()
 
-    # timed region 2: the same solves with HIP events between the passes
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    # timed region 2: the same solves with HIP events between the launches
+    # the tuned schedule runs (passes 1-3 as one range with the plane kernel)
+    runs = launches(tile_sel)
+    nl = len(runs)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)] for _ in range(args.steps)]
     for k in range(args.steps):
         ev[k][0].record(stream)
-        for p in range(5):
-            P.poisson_solve_passes(plan.handle, r, V, p, p, stream)
-            ev[k][p + 1].record(stream)
+        for j, (_, first, last) in enumerate(runs):
+            P.poisson_solve_passes(plan.handle, r, V, first, last, stream)
+            ev[k][j + 1].record(stream)
     torch.cuda.synchronize()
-    per_pass = [float(np.mean([ev[k][p].elapsed_time(ev[k][p + 1]) for k in range(args.steps)]))
-                for p in range(5)]
-    step_ms = np.array([ev[k][0].elapsed_time(ev[k][5]) for k in range(args.steps)])
+    per_pass = [float(np.mean([ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(args.steps)]))
+                for j in range(nl)]
+    step_ms = np.array([ev[k][0].elapsed_time(ev[k][nl]) for k in range(args.steps)])
     step_pct = {f"p{q}": float(np.percentile(step_ms, q)) for q in (10, 50, 90)}
+    names = [name for name, _, _ in runs]
 
-    V_gpu = V.cpu().numpy()
     copy_gbs = copy_bandwidth(torch, dev)
-    pb = pass_bytes(n, info)
+    pb = pass_bytes(n, info, plane=nl == 3)
     dom = int(np.argmax(per_pass))
     achieved = pb[dom] / (per_pass[dom] * 1e-3) / 1e9
-    solve_gbs = info["alg_bytes"] / (ms * 1e-3) / 1e9
+    alg_solve = solve_bytes(n, info, tile_sel)
+    solve_gbs = alg_solve / (ms * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -371,19 +404,19 @@ def main():
                    "gaussians": WORKLOADS[args.workload]["gaussians"], "precision": "fp32",
                    "tile_schedule": list(tile_sel), "tile_lines": list(tile_lines)},
         "untuned_ms_per_step": untuned_ms,
-        "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(PASS_NAMES[dom]) if args.workload == "free256"
+                     "traffic": (measured_traffic(names[dom]) if args.workload == "free256"
                                  else None),
                      "alg_bytes_per_launch": pb[dom],
                      "launch_ms": per_pass[dom]},
-        "solve_roofline": {"alg_bytes": info["alg_bytes"], "achieved": solve_gbs,
+        "solve_roofline": {"alg_bytes": alg_solve, "achieved": solve_gbs,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": solve_gbs / HBM_PEAK_GBS},
         "copy_gbs": copy_gbs,
         "solve_vs_copy": solve_gbs / copy_gbs,
-        "passes_ms": dict(zip(PASS_NAMES, per_pass)),
-        "step_ms_percentiles": step_pct,  # per solve, from the per-pass event loop
-        "passes_gbs": {PASS_NAMES[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(5)},
+        "passes_ms": dict(zip(names, per_pass)),
+        "step_ms_percentiles": step_pct,  # per solve, from the per-launch event loop
+        "passes_gbs": {names[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(nl)},
     }
     out["host_transfer"] = bench_host(torch, P, plan, r)
     # split-precision modes on the same workload: time and accuracy

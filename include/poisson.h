@@ -132,7 +132,11 @@ int poisson_kernel_set(poisson_plan_t plan, const double *kf_octant, int is_devi
 
 /* Build the default Green's function of the plan's boundary conditions on
  * the device in float64 and set it as with poisson_kernel_set.  Asynchronous
- * on `stream`.  Kernel family (the paper cites but does not define it): on
+ * on `stream`: enqueues the build and returns; the plan's workspace serves
+ * as float64 scratch (the first call on a plan without a workspace
+ * allocates it, as poisson_kernel_set does), so nothing else is allocated
+ * and the host does not wait.  Solves enqueued after it on the same stream
+ * see the new K^F.  Kernel family (the paper cites but does not define it): on
  * periodic axes the spectral wave numbers k_j = 2 pi f_j / (S_j h), on the
  * d free axes the sampled Green's function of (lap_d - kappa^2), kappa^2 =
  * sum of periodic k_j^2, times h^d:
@@ -145,7 +149,10 @@ int poisson_kernel_build(poisson_plan_t plan, void *stream);
  * poisson_kernel_set).  Synchronous. */
 int poisson_kernel_get(poisson_plan_t plan, double *kf_octant_host);
 
-/* V = K * rho for one density (device pointers, float32, layout above).
+/* V = K * rho for one density (device pointers, float32, layout above):
+ * the discrete convolution of Eq. 2 evaluated as Eq. 3, V^F = K^F rho^F,
+ * with the customized zero-padded 3D FFT of Section 3 (padding skipped in
+ * the forward transform, crops after the inverse).
  * rho == V (in place) is allowed.  Enqueues five passes on `stream` and
  * returns without waiting; performs no allocation and no host sync, so it
  * can be captured into a HIP graph once the workspace exists (the plan
@@ -266,7 +273,9 @@ int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lin
  * is kept only if it still beats the starting one when both are timed
  * again (alternately, best of two each).  Runs solves on
  * rho_dev and V_dev: V_dev (and the workspace) receive scratch values.
- * pass_ms (may be NULL) receives the chosen schedule's per-pass times.
+ * pass_ms (may be NULL) receives the chosen schedule's per-launch times:
+ * one per pass, or, when it runs passes 1-3 as the plane kernel, that
+ * launch's time in pass_ms[1] and 0 in pass_ms[2] and pass_ms[3].
  * reps <= 0 means 10.  Needs K^F and a workspace; synchronous. */
 int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, int reps,
                       double pass_ms[5], void *stream);

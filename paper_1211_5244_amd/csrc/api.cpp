@@ -206,6 +206,21 @@ int finish_kernel(poisson_plan_t P, hipStream_t s) {
   return POISSON_OK;
 }
 
+// Enqueues the float64 build of the default K^F and its float32 permuted
+// copy on stream s.  The DCT ping-pong's float64 scratch (one octant) lives
+// in `scratch`, a workspace the solves use between builds: the workspace of
+// a solve always has room for it (S_q/2+1 <= S_q and S_r/2+1 <= N_r+1, so
+// the octant is at most the A2 array plus S_q H complex values of A1).
+int build_kernel_into(poisson_plan_t P, void *scratch, size_t scratch_bytes, hipStream_t s) {
+  const size_t need = sizeof(double) * size_t(P->g.kf_octant);
+  if (!scratch || scratch_bytes < need)
+    return fail(POISSON_E_STATE, "no workspace to build K^F in (poisson_set_workspace first)");
+  const double *tabs[3] = {P->cos_tab[0], P->cos_tab[1], P->cos_tab[2]};
+  hipError_t e = psn::launch_kernel_build(P->g, P->h, P->kf64, static_cast<double *>(scratch), tabs, s);
+  if (e != hipSuccess) return hip_fail(e, "K^F build");
+  return finish_kernel(P, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -390,16 +405,7 @@ int poisson_kernel_build(poisson_plan_t P, void *stream) {
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
   int rc = ensure_workspace(P);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // float64 scratch for the DCT ping-pong
-  void *tmp = nullptr;
-  PSN_TRY_HIP(hipMalloc(&tmp, sizeof(double) * P->g.kf_octant), "hipMalloc(K^F scratch)");
-  const double *tabs[3] = {P->cos_tab[0], P->cos_tab[1], P->cos_tab[2]};
-  hipError_t e = psn::launch_kernel_build(P->g, P->h, P->kf64, static_cast<double *>(tmp), tabs, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(tmp);
-  if (e != hipSuccess) return hip_fail(e, "K^F build");
-  return finish_kernel(P, s);
+  return build_kernel_into(P, P->ws, P->ws ? P->g.ws_bytes : 0, static_cast<hipStream_t>(stream));
 }
 
 int poisson_kernel_get(poisson_plan_t P, double *host) {
@@ -610,8 +616,11 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n, const un
 
 int poisson_batch_kernel_build(poisson_batch_t B, void *stream) {
   if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  DeviceScope ds(B->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the batch's device");
+  // the batch workspace holds at least one solve of every distinct problem
   for (auto *P : B->plans) {
-    int rc = poisson_kernel_build(P, stream);
+    int rc = build_kernel_into(P, B->ws, B->ws_bytes, static_cast<hipStream_t>(stream));
     if (rc) return rc;
   }
   return POISSON_OK;
@@ -816,18 +825,26 @@ int tune_plan_passes(poisson_plan_t P, int count, const float *const *rho, float
       return hip_fail(he, "hipEventCreate");
     }
   }
+  // the launches the chosen schedule runs: five passes, or with the plane
+  // kernel pass 0, passes 1-3 as one launch (reported as pass 1) and pass 4
+  const bool plane = (P->g.pass[2].tile_sel & psn::kPlaneBit) && psn::plane_available(P->g, P->precision);
+  const int ranges[5][2] = {{0, 0}, {1, 1}, {2, 2}, {3, 3}, {4, 4}};
+  const int plane_ranges[3][2] = {{0, 0}, {1, 3}, {4, 4}};
+  const int plane_slot[3] = {0, 1, 4};
+  const int nl = plane ? 3 : 5;
   double acc[5] = {0, 0, 0, 0, 0};
   for (int r = 0; r < reps && rc == POISSON_OK; ++r) {
     hipError_t he = hipEventRecord(ev[0], s);
-    for (int k = 0; k < 5 && he == hipSuccess && rc == POISSON_OK; ++k) {
-      rc = enqueue_passes(P, count, rho, V, ws, k, k, s);
+    for (int k = 0; k < nl && he == hipSuccess && rc == POISSON_OK; ++k) {
+      const int *rg = plane ? plane_ranges[k] : ranges[k];
+      rc = enqueue_passes(P, count, rho, V, ws, rg[0], rg[1], s);
       if (rc == POISSON_OK) he = hipEventRecord(ev[k + 1], s);
     }
-    if (he == hipSuccess) he = hipEventSynchronize(ev[5]);
-    for (int k = 0; k < 5 && he == hipSuccess; ++k) {
+    if (he == hipSuccess) he = hipEventSynchronize(ev[nl]);
+    for (int k = 0; k < nl && he == hipSuccess; ++k) {
       float t = 0.f;
       he = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-      acc[k] += t;
+      acc[plane ? plane_slot[k] : k] += t;
     }
     if (he != hipSuccess && rc == POISSON_OK) rc = hip_fail(he, "timing events");
   }
