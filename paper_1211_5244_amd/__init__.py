@@ -45,6 +45,7 @@ from ._lib import (  # noqa: F401
     poisson_plan_set_schedule,
     poisson_plan_tune,
     poisson_rel_l2,
+    poisson_rel_l2_noalloc,
     poisson_set_workspace,
     poisson_solve,
     poisson_solve_host,
@@ -76,6 +77,10 @@ class Plan:
         self.handle = poisson_plan_ordered(*self.n, self.bc_mask, self.h, precision, axis_order)
         self.info = poisson_plan_info(self.handle)
         if build_kernel:
+            # asynchronous: solves enqueued later on the same stream see K^F
+            if stream is None:
+                import torch
+                stream = torch.cuda.current_stream()
             poisson_kernel_build(self.handle, stream)
 
     @property
@@ -151,6 +156,9 @@ class Batch:
     def __init__(self, n_list, bc_list, h_list, precision=POISSON_FP32, stream=None):
         self.n_list = [tuple(int(v) for v in n) for n in n_list]
         self.handle = poisson_batch_create(self.n_list, list(bc_list), list(h_list), precision)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
         poisson_batch_kernel_build(self.handle, stream)
 
     def solve(self, rho_list, V_list, stream=None):

@@ -66,6 +66,20 @@ def test_kernel_build_matches_oracle(torch_dev, n, bc):
     assert d <= KF_REL
 
 
+@pytest.mark.parametrize("n,bc", [((256, 256, 256), 7), ((192, 192, 384), 3), ((384, 192, 384), 2)])
+def test_kernel_build_matches_oracle_full_size(torch_dev, n, bc):
+    """The float64 builder at the benchmark sizes: the 257-point DCT-I sums of
+    the free 256^3 problem and the K0 of large kappa r on the 384-length
+    wire and surface grids, against the oracle's FFT of the sampled kernel."""
+    plan = P.Plan(n, bc, H)
+    kf = plan.kernel()
+    plan.close()
+    ref = oracle.kernel_octant(n, bc, H)
+    d = float(np.max(np.abs(kf - ref)) / np.max(np.abs(ref)))
+    print(f"K^F {n} bc={bc}: {d:.2e}", flush=True)
+    assert d <= KF_REL
+
+
 @pytest.mark.parametrize("bc", range(8))
 @pytest.mark.parametrize("n", SMALL_SHAPES)
 def test_solve_parity_small(torch_dev, n, bc):
