@@ -32,6 +32,7 @@
 #include <type_traits>
 
 #include "fft_core.h"
+#include "fft_mfma.h"
 #include "fft_split.h"
 #include "kernels.h"
 
@@ -143,7 +144,12 @@ struct PassParams {
 // (MODE_FP32), or radix-8 stages as split-precision DFT matmuls on the
 // matrix cores (MODE_SPLIT_*).  `line` is this line group's LDS region,
 // `wave_lines` the first region of its wavefront.
-template <int L, int MODE> struct LineEngine {
+// Engine kinds: 0 float32 radix stages, 1 radix-8 matrix stages with LDS
+// exchanges (fft_split.h), 2 the two-factor matrix-core engine.
+template <int L, int MODE> constexpr int engine_kind() {
+  return MODE == MODE_FP32 ? 0 : mfma_length<L>() ? 2 : 1;
+}
+template <int L, int MODE, int KIND = engine_kind<L, MODE>()> struct LineEngine {
   SplitTwiddles<L> tw;
   SplitOps<MODE> ops;
   __device__ __forceinline__ void init(const float2 *tab, int lane) {
@@ -158,7 +164,18 @@ template <int L, int MODE> struct LineEngine {
     fft_line_split<L, INV, MODE, ZHI, CROP>(v, tw, ops, wave_lines, lane);
   }
 };
-template <int L> struct LineEngine<L, MODE_FP32> {
+// Lengths 32..512 of the form 16 B: the two-factor matrix-core engine
+// (fft_mfma.h), whose matrix stages exchange no data through LDS.
+template <int L, int MODE> struct LineEngine<L, MODE, 2> {
+  MfmaLine<L, MODE> m;
+  __device__ __forceinline__ void init(const float2 *tab, int lane) { m.init(tab, lane); }
+  template <bool INV, bool ZHI = false, bool CROP = false>
+  __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
+                                      int lane) {
+    m.template run<INV, ZHI, CROP>(v, wave_lines, lane);
+  }
+};
+template <int L> struct LineEngine<L, MODE_FP32, 0> {
   Twiddles<L> tw;
   __device__ __forceinline__ void init(const float2 *tab, int lane) { tw.load(tab, lane % kT<L>); }
   // (a cropped output needs nothing here: unstored outputs are dead code)
@@ -166,6 +183,52 @@ template <int L> struct LineEngine<L, MODE_FP32> {
   __device__ __forceinline__ void run(float2 (&v)[Shape<L>::E], float2 *line, float2 *wave_lines,
                                       int lane) {
     fft_line<L, INV, ZHI>(v, tw, line, lane % kT<L>);
+  }
+};
+
+// Direct layouts of the two-factor engine for lengths with 8 elements per
+// lane (32 ... 512, powers of two): a pass moves data straight between HBM
+// (or its LDS tile) and the engine's operand layouts, with no canonical
+// exchange around the transform.  Register i of a lane is element
+// `*_index(lane, i)` of wavefront line `*_line(lane, i)` (-1: not an
+// element, e.g. the zero-padded half), for the forward input, the spectrum
+// (forward output = inverse input) and the inverse output.
+template <int L, int MODE> struct Direct {
+  static constexpr bool ON = engine_kind<L, MODE>() == 2 && Shape<L>::E == 8;
+  using Eng = MfmaLine<L, MODE == MODE_FP32 ? MODE_SPLIT_FP16 : MODE>;
+  static constexpr int KB = Eng::KB, P = Eng::P, NB = Eng::NB;
+  __device__ __forceinline__ static int blk(int i) { return i / (4 * KB); }
+  __device__ __forceinline__ static int kb(int i) { return (i / 4) % KB; }
+  __device__ __forceinline__ static int in_line(int lane, int i) { return blk(i) * P + Eng::in_line(lane, kb(i), i % 4); }
+  template <bool ZHI> __device__ __forceinline__ static int in_index(int lane, int i) {
+    return Eng::template in_index<ZHI>(lane, kb(i), i % 4);
+  }
+  __device__ __forceinline__ static int spec_line(int lane, int i) { return blk(i) * P + Eng::spec_line(lane, kb(i)); }
+  __device__ __forceinline__ static int spec_index(int lane, int i) { return Eng::spec_index(lane, kb(i), i % 4); }
+  __device__ __forceinline__ static int out_line(int lane, int i) { return blk(i) * P + Eng::out_line(lane, kb(i), i % 4); }
+  template <bool CROP> __device__ __forceinline__ static int out_index(int lane, int i) {
+    return Eng::template out_index<CROP>(lane, kb(i), i % 4);
+  }
+  // forward (v in the input layout -> spectrum) or inverse (spectrum ->
+  // output layout) of the wavefront's blocks, unnormalized, in registers
+  template <bool INV, bool ZHI, bool CROP>
+  __device__ __forceinline__ static void transform(const Eng &e, float2 (&v)[8], int lane) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      float2 x[KB][4];
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) x[k][l] = v[(b * KB + k) * 4 + l];
+      int s[KB][4];
+      if constexpr (INV) e.template inverse<CROP>(x, s, lane);
+      else e.template forward<ZHI>(x, s, lane);
+      Eng::unscale(x, s);
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) v[(b * KB + k) * 4 + l] = x[k][l];
+    }
   }
 };
 
@@ -272,6 +335,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
   LineEngine<L, MODE> eng;
   eng.init(a.tw, lane);
 
+  using D = Direct<L, MODE>;
   TileRegs<ROWS_IN, W, NT, LD, float2> pf;
   float2 vn[E];
   auto fetch = [&](int tile) {
@@ -279,6 +343,14 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
     const float2 *__restrict__ in = static_cast<const float2 *>(a.in[q.solve]);
     if constexpr (IN_TILED) {
       pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
+    } else if constexpr (D::ON) {
+      // straight into the engine's input (forward) or spectrum (inverse) layout
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int lc = wave * LPW + (INV ? D::spec_line(lane, i) : D::in_line(lane, i));
+        const int n = INV ? D::spec_index(lane, i) : D::template in_index<PAD>(lane, i);
+        vn[i] = (n >= 0 && lc < q.ncols) ? in[(q.a0 + lc) * a.in_st + q.b * a.in_sb + n] : make_float2(0.f, 0.f);
+      }
     } else {
       const bool ok = c < q.ncols;
       const float2 *line = in + (q.a0 + c) * a.in_st + q.b * a.in_sb;
@@ -298,10 +370,19 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
     if constexpr (IN_TILED) {
       pf.to_lds(smem, tid);
       __syncthreads();
-      const bool ok = c < q.ncols;  // columns past a ragged edge hold stale LDS
+      if constexpr (D::ON) {
 #pragma unroll
-      for (int i = 0; i < E; ++i)
-        v[i] = ((!PAD || i < E / 2) && ok) ? smem[(t + T * i) * LD + c] : make_float2(0.f, 0.f);
+        for (int i = 0; i < E; ++i) {
+          const int lc = wave * LPW + (INV ? D::spec_line(lane, i) : D::in_line(lane, i));
+          const int n = INV ? D::spec_index(lane, i) : D::template in_index<PAD>(lane, i);
+          v[i] = (n >= 0 && lc < q.ncols) ? smem[n * LD + lc] : make_float2(0.f, 0.f);
+        }
+      } else {
+        const bool ok = c < q.ncols;  // columns past a ragged edge hold stale LDS
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+          v[i] = ((!PAD || i < E / 2) && ok) ? smem[(t + T * i) * LD + c] : make_float2(0.f, 0.f);
+      }
       if (next < a.ntiles) fetch(next);
       __syncthreads();  // the tile region becomes exchange space
     } else {
@@ -310,16 +391,38 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    eng.template run<INV, PAD, CROP>(v, xch, wave_lines, lane);
+    if constexpr (D::ON) {
+      D::template transform<INV, PAD, CROP>(eng.m, v, lane);
+    } else {
+      eng.template run<INV, PAD, CROP>(v, xch, wave_lines, lane);
+    }
 
     if constexpr (OUT_TILED) {
       __syncthreads();  // every line is done exchanging
+      if constexpr (D::ON) {
 #pragma unroll
-      for (int i = 0; i < E; ++i)
-        if (!CROP || i < E / 2) smem[(t + T * i) * LD + c] = v[i];
+        for (int i = 0; i < E; ++i) {
+          const int lc = wave * LPW + (INV ? D::out_line(lane, i) : D::spec_line(lane, i));
+          const int n = INV ? D::template out_index<CROP>(lane, i) : D::spec_index(lane, i);
+          if (n >= 0) smem[n * LD + lc] = v[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+          if (!CROP || i < E / 2) smem[(t + T * i) * LD + c] = v[i];
+      }
       __syncthreads();
       tile_store<ROWS_OUT, W, NT, LD>(static_cast<float2 *>(a.out[q.solve]) + q.b * a.out_sb + q.a0,
                                       a.out_sl, q.ncols, smem, tid);
+    } else if constexpr (D::ON) {
+      float2 *out = static_cast<float2 *>(a.out[q.solve]);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int lc = wave * LPW + (INV ? D::out_line(lane, i) : D::spec_line(lane, i));
+        const int n = INV ? D::template out_index<CROP>(lane, i) : D::spec_index(lane, i);
+        // 16 lanes cover 16 consecutive elements (128 bytes) of one line
+        if (n >= 0 && lc < q.ncols) st_out<128>(&out[(q.a0 + lc) * a.out_st + q.b * a.out_sb + n], v[i]);
+      }
     } else {
       if (c < q.ncols) {
         float2 *line = static_cast<float2 *>(a.out[q.solve]) + (q.a0 + c) * a.out_st + q.b * a.out_sb;
@@ -352,6 +455,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
   LineEngine<L, MODE> eng;
   eng.init(a.tw, lane);
 
+  using D = Direct<L, MODE>;
   TileRegs<ROWS_IN, W, NT, LDR, float> pf;
   float2 vn[E];
   auto fetch = [&](int tile) {
@@ -359,6 +463,17 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
     const float *__restrict__ in = static_cast<const float *>(a.in[q.solve]);
     if constexpr (IN_TILED) {
       pf.load(in + q.b * a.in_sb + q.a0, a.in_sl, q.ncols, tid);
+    } else if constexpr (D::ON) {
+      // real lines 2 lc and 2 lc + 1 as one complex line, in the engine's
+      // input layout
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int lc = wave * LPW + D::in_line(lane, i);
+        const int n = D::template in_index<PAD>(lane, i);
+        const float *l0 = in + (q.a0 + 2 * lc) * a.in_st + q.b * a.in_sb;
+        vn[i].x = (n >= 0 && 2 * lc < q.ncols) ? l0[n] : 0.f;
+        vn[i].y = (n >= 0 && 2 * lc + 1 < q.ncols) ? l0[a.in_st + n] : 0.f;
+      }
     } else {
       const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
       const float *l0 = in + (q.a0 + 2 * c) * a.in_st + q.b * a.in_sb;
@@ -382,13 +497,24 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
     if constexpr (IN_TILED) {
       pf.to_lds(smem_f, tid);
       __syncthreads();
-      const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
+      if constexpr (D::ON) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        const float2 x = (!PAD || i < E / 2)
-                             ? *reinterpret_cast<const float2 *>(smem_f + (t + T * i) * LDR + 2 * c)
-                             : make_float2(0.f, 0.f);
-        v[i] = make_float2(ok0 ? x.x : 0.f, ok1 ? x.y : 0.f);
+        for (int i = 0; i < E; ++i) {
+          const int lc = wave * LPW + D::in_line(lane, i);
+          const int n = D::template in_index<PAD>(lane, i);
+          const float2 x = n >= 0 ? *reinterpret_cast<const float2 *>(smem_f + n * LDR + 2 * lc)
+                                  : make_float2(0.f, 0.f);
+          v[i] = make_float2(2 * lc < q.ncols ? x.x : 0.f, 2 * lc + 1 < q.ncols ? x.y : 0.f);
+        }
+      } else {
+        const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const float2 x = (!PAD || i < E / 2)
+                               ? *reinterpret_cast<const float2 *>(smem_f + (t + T * i) * LDR + 2 * c)
+                               : make_float2(0.f, 0.f);
+          v[i] = make_float2(ok0 ? x.x : 0.f, ok1 ? x.y : 0.f);
+        }
       }
       if (next < a.ntiles) fetch(next);
       __syncthreads();
@@ -398,12 +524,23 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
       if (next < a.ntiles) fetch(next);
     }
 
-    eng.template run<false, PAD>(v, xch, wave_lines, lane);
-
     // separate the two real lines: needs Z[L - k] from the mirrored lane
+    if constexpr (D::ON) {
+      D::template transform<false, PAD, false>(eng.m, v, lane);
 #pragma unroll
-    for (int i = 0; i < E; ++i) xch[lds_pad(t + T * i)] = v[i];
-    wave_lds_fence();
+      for (int i = 0; i < E; ++i) {
+        const int k = D::spec_index(lane, i);
+        if (k >= 0) wave_lines[D::spec_line(lane, i) * C::SLOTS + lds_pad(k)] = v[i];
+      }
+      wave_lds_fence();
+#pragma unroll
+      for (int i = 0; i <= E / 2; ++i) v[i] = xch[lds_pad(t + T * i < L ? t + T * i : 0)];
+    } else {
+      eng.template run<false, PAD>(v, xch, wave_lines, lane);
+#pragma unroll
+      for (int i = 0; i < E; ++i) xch[lds_pad(t + T * i)] = v[i];
+      wave_lds_fence();
+    }
     float2 x0[E / 2 + 1], x1[E / 2 + 1];
 #pragma unroll
     for (int i = 0; i <= E / 2; ++i) {
@@ -450,6 +587,7 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
   LineEngine<L, MODE> eng;
   eng.init(a.tw, lane);
 
+  using D = Direct<L, MODE>;
   TileRegs<ROWS_IN, W, NT, LDC, float2> pf;
   int tile = block_order(a.xcd);
   if (tile < a.ntiles) {
@@ -463,14 +601,17 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
     __syncthreads();
     pf.to_lds(smem, tid);
     __syncthreads();
-    const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const int k = t + T * i;
-      const bool direct = i < E / 2 || k == L / 2;
-      const int kk = direct ? k : L - k;
-      float2 x0 = ok0 ? smem[kk * LDC + 2 * c] : make_float2(0.f, 0.f);
-      float2 x1 = ok1 ? smem[kk * LDC + 2 * c + 1] : make_float2(0.f, 0.f);
+      // register i holds spectrum index k of complex line lc (the engine's
+      // input layout, or lane t's strided elements)
+      const int lc = D::ON ? wave * LPW + D::spec_line(lane, i) : c;
+      const int k = D::ON ? D::spec_index(lane, i) : t + T * i;
+      const bool ok0 = k >= 0 && 2 * lc < q.ncols, ok1 = k >= 0 && 2 * lc + 1 < q.ncols;
+      const bool direct = k <= L / 2;
+      const int kk = k < 0 ? 0 : direct ? k : L - k;
+      float2 x0 = ok0 ? smem[kk * LDC + 2 * lc] : make_float2(0.f, 0.f);
+      float2 x1 = ok1 ? smem[kk * LDC + 2 * lc + 1] : make_float2(0.f, 0.f);
       if (kk == 0 || kk == L / 2) {
         // DC and Nyquist coefficients of a real line are real
         x0.y = 0.f;
@@ -486,17 +627,34 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
     }
     __syncthreads();
 
-    eng.template run<true, false, CROP>(v, xch, wave_lines, lane);
+    if constexpr (D::ON) {
+      D::template transform<true, false, CROP>(eng.m, v, lane);
+    } else {
+      eng.template run<true, false, CROP>(v, xch, wave_lines, lane);
+    }
 
     if constexpr (OUT_TILED) {
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < E; ++i)
-        if (!CROP || i < E / 2)
-          *reinterpret_cast<float2 *>(smem_f + (t + T * i) * LDR + 2 * c) = v[i];
+      for (int i = 0; i < E; ++i) {
+        const int lc = D::ON ? wave * LPW + D::out_line(lane, i) : c;
+        const int n = D::ON ? D::template out_index<CROP>(lane, i) : ((!CROP || i < E / 2) ? t + T * i : -1);
+        if (n >= 0) *reinterpret_cast<float2 *>(smem_f + n * LDR + 2 * lc) = v[i];
+      }
       __syncthreads();
       tile_store<ROWS_OUT, W, NT, LDR>(static_cast<float *>(a.out[q.solve]) + q.b * a.out_sb + q.a0,
                                        a.out_sl, q.ncols, smem_f, tid);
+    } else if constexpr (D::ON) {
+      float *out = static_cast<float *>(a.out[q.solve]);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int lc = wave * LPW + D::out_line(lane, i);
+        const int n = D::template out_index<CROP>(lane, i);
+        float *l0 = out + (q.a0 + 2 * lc) * a.out_st + q.b * a.out_sb;
+        // 16 lanes cover 64 contiguous bytes of each real line
+        if (n >= 0 && 2 * lc < q.ncols) st_out<64>(&l0[n], v[i].x);
+        if (n >= 0 && 2 * lc + 1 < q.ncols) st_out<64>(&l0[a.out_st + n], v[i].y);
+      }
     } else {
       const bool ok0 = 2 * c < q.ncols, ok1 = 2 * c + 1 < q.ncols;
       float *l0 = static_cast<float *>(a.out[q.solve]) + (q.a0 + 2 * c) * a.out_st + q.b * a.out_sb;
@@ -572,20 +730,36 @@ __attribute__((amdgpu_waves_per_eu(conv_min_waves<L>()))) void conv_kernel(ConvP
     float2 *line;
     bool live;
   };
+  // One line per wavefront on the two-factor matrix-core engine: the line
+  // is loaded straight into the engine's operand layout and the kernel
+  // values into its spectrum layout, so the fused transform exchanges
+  // nothing through LDS.
+  constexpr bool FUSED = engine_kind<L, MODE>() == 2 && LPW == 1;
+  using Eng = MfmaLine<L, MODE == MODE_FP32 ? MODE_SPLIT_FP16 : MODE>;
   auto fetch = [&](Item &it) {
     it.live = solve < a.nsolve;
     const int kq = rep == 0 ? kqf : a.S_q - kqf;
     it.line = a.data + (it.live ? solve * a.solve_stride + (kp * a.st_p + kq * a.st_q) : 0);
     const float *krow = a.kf + (it.live ? (kp * a.kq_half + kqf) * KR : 0);
-    // K^F is even along r: element k >= L/2 takes row entry L - k (i >= E/2
-    // holds exactly those k, and k = L/2 reads the same entry either way)
-    const float *kup = krow + t, *kdown = krow + (L - t);
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int k = t + T * i;
-      it.k[i] = i < E / 2 ? kup[T * i] : kdown[-T * i];
-      // the padding half: never read by the float32 first stage
-      it.v[i] = (!PC || i < E / 2) ? it.line[k] : make_float2(0.f, 0.f);
+      for (int i = 0; i < E; ++i) {
+        const int n = Eng::template in_index<PC>(lane, i / 4, i % 4);
+        it.v[i] = n >= 0 ? it.line[n] : make_float2(0.f, 0.f);
+        const int k = Eng::spec_index(lane, i / 4, i % 4);  // 0 <= k < L
+        it.k[i] = krow[k <= L / 2 ? k : L - k];
+      }
+    } else {
+      // K^F is even along r: element k >= L/2 takes row entry L - k (i >= E/2
+      // holds exactly those k, and k = L/2 reads the same entry either way)
+      const float *kup = krow + t, *kdown = krow + (L - t);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int k = t + T * i;
+        it.k[i] = i < E / 2 ? kup[T * i] : kdown[-T * i];
+        // the padding half: never read by the float32 first stage
+        it.v[i] = (!PC || i < E / 2) ? it.line[k] : make_float2(0.f, 0.f);
+      }
     }
   };
   auto advance = [&]() {
@@ -608,14 +782,33 @@ __attribute__((amdgpu_waves_per_eu(conv_min_waves<L>()))) void conv_kernel(ConvP
     }
   };
   auto process = [&](Item &it) {
-    eng.template run<false, PC>(it.v, xch, wave_lines, lane);
+    if constexpr (FUSED) {
+      constexpr int KB = Eng::KB;
+      float2 x[KB][4];
+      float kv[KB][4];
 #pragma unroll
-    for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
-    eng.template run<true, false, PC>(it.v, xch, wave_lines, lane);
-    if (it.live) {
+      for (int i = 0; i < E; ++i) {
+        x[i / 4][i % 4] = it.v[i];
+        kv[i / 4][i % 4] = it.k[i];
+      }
+      eng.m.template conv<PC>(x, kv, lane);
+      if (it.live) {
 #pragma unroll
-      for (int i = 0; i < E; ++i)
-        if (!PC || i < E / 2) st_out<T * 8>(&it.line[t + T * i], it.v[i]);
+        for (int i = 0; i < E; ++i) {
+          const int n = Eng::template out_index<PC>(lane, i / 4, i % 4);
+          if (n >= 0) st_out<128>(&it.line[n], x[i / 4][i % 4]);  // 16 lanes: 128 contiguous bytes
+        }
+      }
+    } else {
+      eng.template run<false, PC>(it.v, xch, wave_lines, lane);
+#pragma unroll
+      for (int i = 0; i < E; ++i) it.v[i] = make_float2(it.v[i].x * it.k[i], it.v[i].y * it.k[i]);
+      eng.template run<true, false, PC>(it.v, xch, wave_lines, lane);
+      if (it.live) {
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+          if (!PC || i < E / 2) st_out<T * 8>(&it.line[t + T * i], it.v[i]);
+      }
     }
   };
 
