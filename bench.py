@@ -241,6 +241,45 @@ def bench_host(torch, P, plan, r, count=20):
                           "pcie_gbs": nbytes / (t_pipe * 1e-3) / 1e9, "solves": count}}
 
 
+class FullPaddedSolve:
+    """The "3D FFT library" comparator of Section 4 and 5: a problem with
+    free axes solved as a periodic problem on the whole padded grid S1 x S2
+    x S3, with no zero skipping and no crop inside the transforms.  The
+    density is zero padded into an S-grid, the periodic plan of that grid
+    gets the problem's own K^F octant (the octants have the same shape), and
+    the potential is cropped back.  Same V as the customized solve; every
+    1D transform runs over all S_p S_q (resp. S_p S_r, S_q S_r) rows."""
+
+    def __init__(self, P, n, bc, h, precision=0):
+        import torch
+        own = P.Plan(n, bc, h, precision=precision)
+        kf = own.kernel()
+        own.close()
+        self.n = tuple(n)
+        self.S = tuple(int(v) * (2 if (bc >> j) & 1 else 1) for j, v in enumerate(n))
+        self.plan = P.Plan(self.S, 0, h, precision=precision, build_kernel=False)
+        self.plan.set_kernel(kf)
+        self.pad = None
+        self.torch = torch
+
+    def solve(self, rho, V, stream=None):
+        n, S = self.n, self.S
+        if self.pad is None:
+            self.pad = self.torch.zeros((S[2], S[1], S[0]), dtype=self.torch.float32, device=rho.device)
+        self.pad.zero_()
+        self.pad[:n[2], :n[1], :n[0]].copy_(rho)
+        self.plan.solve(self.pad, self.pad, stream)
+        V.copy_(self.pad[:n[2], :n[1], :n[0]])
+        return V
+
+    def solve_padded(self, stream=None):
+        """The transforms alone, on the resident padded grid."""
+        self.plan.solve(self.pad, self.pad, stream)
+
+    def close(self):
+        self.plan.close()
+
+
 def fig1(torch, P, dev, steps, warmup):
     """Figure 1's experiment (Section 4): time of each BC class relative to the
     fully periodic solve of the same FFT size S^3, with Section 3's axis-order
@@ -283,6 +322,28 @@ def fig1(torch, P, dev, steps, warmup):
                         "fft_work_vs_periodic": work / base[1],
                         "alg_bytes_vs_periodic": d["alg_bytes"] / base[2]})
             plan.close()
+            if order is None and bc != 0:
+                # the same problem through the full-padded periodic solve
+                fp = FullPaddedSolve(P, n, bc, H)
+                for _ in range(warmup):
+                    fp.solve(r, V, stream)
+                e0.record(stream)
+                for _ in range(steps):
+                    fp.solve(r, V, stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms_fp = e0.elapsed_time(e1) / steps
+                e0.record(stream)
+                for _ in range(steps):
+                    fp.solve_padded(stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms_fft = e0.elapsed_time(e1) / steps
+                out.append({"S": S, "case": name + "_full_padded", "n": list(n), "bc_mask": bc,
+                            "ms": ms_fp, "ms_transforms_only": ms_fft,
+                            "time_vs_periodic": ms_fp / base[0],
+                            "customized_vs_full_padded": ms / ms_fp})
+                fp.close()
             del r, V
     return out
 
@@ -296,6 +357,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-solve batch")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision modes")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default schedules (short runs under a profiler)")
+    ap.add_argument("--no-host", action="store_true", help="skip the host-buffer transfer rates")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy (counter calibration)")
     ap.add_argument("--fig1", action="store_true",
@@ -345,7 +409,8 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     untuned_ms = e0.elapsed_time(e1) / args.steps
-    plan.tune(r, V, stream=stream)
+    if not args.no_tune:
+        plan.tune(r, V, stream=stream)
     tile_sel, tile_lines = plan.schedule
     for _ in range(args.warmup):
         plan.solve(r, V, stream)
@@ -418,14 +483,16 @@ def main():
         "step_ms_percentiles": step_pct,  # per solve, from the per-launch event loop
         "passes_gbs": {names[i]: pb[i] / (per_pass[i] * 1e-3) / 1e9 for i in range(nl)},
     }
-    out["host_transfer"] = bench_host(torch, P, plan, r)
+    if not args.no_host:
+        out["host_transfer"] = bench_host(torch, P, plan, r)
     # split-precision modes on the same workload: time and accuracy
     if not args.no_split:
         out["split"] = {}
         for prec, name in ((P.POISSON_SPLIT_FP16, "fp16x2"), (P.POISSON_SPLIT_BF16, "bf16x3")):
             sp = P.Plan(n, bc, H, precision=prec)
             Vs = torch.empty_like(r)
-            sp.tune(r, Vs, stream=stream)  # tuned, as the float32 plan
+            if not args.no_tune:
+                sp.tune(r, Vs, stream=stream)  # tuned, as the float32 plan
             for _ in range(3):
                 sp.solve(r, Vs, stream)
             torch.cuda.synchronize()
@@ -436,8 +503,27 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) / args.steps
+            Vsplit = Vs.cpu().numpy()
+            # per-launch times of the split solve, as for float32
+            sruns = launches(sp.schedule[0])
+            sev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(sruns) + 1)]
+                   for _ in range(args.steps)]
+            for k in range(args.steps):
+                sev[k][0].record(stream)
+                for j, (_, first, last) in enumerate(sruns):
+                    P.poisson_solve_passes(sp.handle, r, Vs, first, last, stream)
+                    sev[k][j + 1].record(stream)
+            torch.cuda.synchronize()
+            sms = [float(np.mean([sev[k][j].elapsed_time(sev[k][j + 1]) for k in range(args.steps)]))
+                   for j in range(len(sruns))]
+            spb = pass_bytes(n, info, plane=len(sruns) == 3)
             out["split"][name] = {"ms_per_solve": t, "solves_per_s": 1000.0 / t,
-                                  "tile_schedule": list(sp.schedule[0]), "V": Vs.cpu().numpy()}
+                                  "solve_roofline_frac": solve_bytes(n, info, sp.schedule[0]) / (t * 1e-3) / 1e9
+                                  / HBM_PEAK_GBS,
+                                  "passes_ms": {nm: v for (nm, _, _), v in zip(sruns, sms)},
+                                  "passes_frac": {nm: b / (v * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                  for (nm, _, _), b, v in zip(sruns, spb, sms)},
+                                  "tile_schedule": list(sp.schedule[0]), "V": Vsplit}
             sp.close()
     if not args.no_batch:
         out["batch"] = {"workload": "batch512 (edges 32..128, 4 BC classes, 4 Gaussians)",

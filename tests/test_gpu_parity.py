@@ -133,6 +133,23 @@ def test_every_axis_order_matches_oracle(torch_dev, bc):
         _check(V, ref, f"{n} bc={bc} order={order}")
 
 
+@pytest.mark.parametrize("n,bc", [((32, 24, 16), 7), ((24, 16, 32), 3), ((32, 12, 24), 2)])
+def test_full_padded_comparator_matches_oracle(torch_dev, n, bc):
+    """The benchmark's "3D FFT library" comparator (a periodic plan over the
+    whole padded grid with the problem's K^F set through poisson_kernel_set,
+    pad and crop around it) gives the same V as the definition."""
+    import bench
+    torch = torch_dev
+    rho = _density(n, bc, seed=350 + bc)
+    fp = bench.FullPaddedSolve(P, n, bc, H)
+    r = torch.from_numpy(rho).cuda()
+    V = torch.empty_like(r)
+    fp.solve(r, V)
+    torch.cuda.synchronize()
+    _check(V.cpu().numpy(), oracle.solve(rho.astype(np.float64), bc, H), f"full padded {n} bc={bc}")
+    fp.close()
+
+
 def test_host_buffer_solves(torch_dev):
     """Upload, solve and download through pinned host buffers: one at a time,
     in place, and the overlapped many-solve pipeline, all bitwise equal to
