@@ -295,6 +295,21 @@ int poisson_batch_tune(poisson_batch_t batch, const float *const *rho_ptrs, floa
 int poisson_rel_l2(const float *v_dev, const double *ref_dev, size_t count, double *out,
                    void *stream);
 
+/* The residual of poisson_rel_l2 for callers that cannot allocate (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * enqueues the same float64 reduction on `stream` and writes
+ * ||v - ref||_2 / ||ref||_2 to the device double *out_dev, without
+ * allocating and without waiting on the host (capturable into a HIP graph).
+ * Its per-block partial sums (at most 1024 pairs) live in a 16 KiB static
+ * device array of the library that every device holds until the process
+ * ends; the reduction never needs more, so every count is accepted.  All
+ * calls on one device share that array: calls that overlap on one device
+ * (concurrent streams or threads) race.  The result equals poisson_rel_l2's
+ * to float64 rounding (same partial sums, summed in the same order).
+ * POISSON_E_ARG for NULL pointers or count == 0. */
+int poisson_rel_l2_noalloc(const float *v_dev, const double *ref_dev, size_t count,
+                           double *out_dev, void *stream);
+
 /* Message of the calling thread's last failed call ("" if none). */
 const char *poisson_last_error(void);
 

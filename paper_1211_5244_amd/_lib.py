@@ -35,7 +35,8 @@ EXPORTED = (
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
     "poisson_batch_set_schedule", "poisson_batch_get_schedule", "poisson_plan_get_schedule",
-    "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2", "poisson_last_error",
+    "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2", "poisson_rel_l2_noalloc",
+    "poisson_last_error",
 )
 
 # schedules per pass (poisson_plan_set_schedule): tile width in bits 0-1,
@@ -102,6 +103,7 @@ def load_library(path=None):
         "poisson_batch_tune": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                                     ctypes.POINTER(_d), _vp]),
         "poisson_rel_l2": (_i, [_vp, _vp, _sz, ctypes.POINTER(_d), _vp]),
+        "poisson_rel_l2_noalloc": (_i, [_vp, _vp, _sz, _vp, _vp]),
         "poisson_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -271,6 +273,13 @@ def poisson_rel_l2(v, ref, count, stream=None):
     out = _d()
     _check(load_library().poisson_rel_l2(_ptr(v), _ptr(ref), count, ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def poisson_rel_l2_noalloc(v, ref, count, out_dev, stream=None):
+    """Enqueues the residual; the float64 result lands in device memory
+    out_dev (a tensor or an address)."""
+    _check(load_library().poisson_rel_l2_noalloc(_ptr(v), _ptr(ref), count, _ptr(out_dev),
+                                                 _stream(stream)))
 
 
 def poisson_plan_set_schedule(plan, tile_sel):

@@ -961,4 +961,12 @@ int poisson_rel_l2(const float *v, const double *ref, size_t count, double *out,
   return POISSON_OK;
 }
 
+int poisson_rel_l2_noalloc(const float *v, const double *ref, size_t count, double *out_dev,
+                           void *stream) {
+  if (!v || !ref || !out_dev || count == 0) return fail(POISSON_E_ARG, "NULL argument or empty input");
+  hipError_t e = psn::launch_rel_l2_noalloc(v, ref, count, out_dev, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "relative L2 norm (static scratch)");
+  return POISSON_OK;
+}
+
 }  // extern "C"

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -227,6 +228,66 @@ hipError_t launch_kernel_permute(const Geometry &g, const double *kf64, float *k
   p.scale = 1.0 / (double(g.S[0]) * g.S[1] * g.S[2]);
   const long long n = (long long)p.E[0] * p.E[1] * p.E[2];
   hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, kf64, kf32);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- allocation-free residual
+// The per-block partial sums of the allocation-free residual live in this
+// file-scope device array (16 KiB, held by every device the library runs
+// on until the process ends).  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr int kScratchBlocks = 1024;
+static __device__ __align__(256) double scratch[2 * kScratchBlocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first call).
+hipError_t scratch_address(double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Sum of the block partials in block order (the order the host sum of
+// poisson_rel_l2 uses), then sqrt(num / den) with the same zero cases.
+__global__ void rel_l2_final_kernel(const double *partials, int blocks, double *out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double num = 0.0, den = 0.0;
+  for (int b = 0; b < blocks; ++b) {
+    num += partials[2 * b];
+    den += partials[2 * b + 1];
+  }
+  *out = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? HUGE_VAL : 0.0);
+}
+
+}  // namespace
+
+hipError_t launch_rel_l2_noalloc(const float *v, const double *ref, size_t count, double *out,
+                                 hipStream_t s) {
+  double *partials = nullptr;
+  hipError_t e = scratch_address(&partials);
+  if (e != hipSuccess) return e;
+  int blocks = 0;
+  e = launch_rel_l2_partials(v, ref, count, partials, kScratchBlocks, &blocks, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rel_l2_final_kernel, dim3(1), dim3(64), 0, s, (const double *)partials, blocks,
+                     out);
   return hipGetLastError();
 }
 

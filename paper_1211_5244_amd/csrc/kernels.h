@@ -70,4 +70,11 @@ hipError_t launch_rel_l2_partials(const float *v, const double *ref, size_t coun
                                   double *partials, int max_blocks, int *blocks,
                                   hipStream_t stream);
 
+// The same residual with its partial sums in the library's static device
+// scratch and the result, ||v - ref|| / ||ref||, written to device memory
+// `out`: no allocation, no host wait.  Calls that overlap on one device
+// share the scratch and race.
+hipError_t launch_rel_l2_noalloc(const float *v, const double *ref, size_t count, double *out,
+                                 hipStream_t stream);
+
 }  // namespace psn

@@ -189,6 +189,8 @@ def test_null_handles_of_the_later_entry_points():
     assert lib.poisson_solve_host(None, None, None, None) == E
     assert lib.poisson_solve_host_many(None, 1, None, None, None) == E
     assert lib.poisson_plan_info(None, None, None, None, None) == E
+    assert lib.poisson_rel_l2_noalloc(None, None, 0, None, None) == E
+    assert lib.poisson_rel_l2_noalloc(None, None, 16, None, None) == E
     out = ctypes.c_void_p()
     bad = (ctypes.c_int * 3)(0, 0, 1)
     assert lib.poisson_plan_ordered(ctypes.byref(out), 8, 8, 8, 7, 0.3, 0, bad) == E
