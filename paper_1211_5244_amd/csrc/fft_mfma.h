@@ -109,6 +109,21 @@ template <bool CONJ> __device__ __forceinline__ void split_leg(float re, float i
         : "=&v"(hi), "=&v"(lo)
         : "v"(re), "v"(im), "v"(sc));
 }
+// The same split with no scale (sc = 1): hi by one packed conversion.
+template <bool CONJ> __device__ __forceinline__ void split_leg1(float re, float im, unsigned &hi, unsigned &lo) {
+  if constexpr (!CONJ)
+    asm("v_cvt_pk_f16_f32 %0, %2, %3\n\t"
+        "v_fma_mixlo_f16 %1, 1.0, %2, -%0 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %1, 1.0, %3, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(hi), "=&v"(lo)
+        : "v"(re), "v"(im));
+  else
+    asm("v_cvt_pk_f16_f32 %0, %2, -%3\n\t"
+        "v_fma_mixlo_f16 %1, 1.0, %2, -%0 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %1, 1.0, -%3, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(hi), "=&v"(lo)
+        : "v"(re), "v"(im));
+}
 // -i times a packed leg: (re, im) -> (im, -re), exact
 __device__ __forceinline__ unsigned rot_leg(unsigned v) {
   unsigned r;
@@ -147,33 +162,42 @@ __device__ __forceinline__ void split_leg_bf16(float re, float im, unsigned &h, 
 // The matrix cores read their A and B operands a few cycles after issue,
 // and a vector-ALU write shortly before can be missed.  The compiler inserts
 // the wait states for its own instructions but cannot see which registers
-// the inline assembly above writes, so every finished operand set passes
+// the inline assembly above writes, so every finished operand passes
 // through this fence: a wait whose in/out operands are the operand
-// registers, which orders every matrix product that reads them after it.
+// registers, so every matrix product that reads them comes after it (by
+// data dependence: the fence is not volatile and does not hold back other
+// instructions).
 // (Without it, schedules under high register pressure read stale operand
 // halves: the length-384 inverse passes went wrong by up to 1e-2.)
-template <int MODE> __device__ __forceinline__ void operand_fence(MOp<MODE> &o, MOp<MODE> &r) {
+template <int MODE> __device__ __forceinline__ void operand_fence(MOp<MODE> &o) {
   if constexpr (MODE == MODE_SPLIT_FP16)
-    asm volatile("s_nop 4" : "+v"(o.hi), "+v"(o.lo), "+v"(r.hi), "+v"(r.lo));
+    asm("s_nop 2" : "+v"(o.hi), "+v"(o.lo));
   else
-    asm volatile("s_nop 4" : "+v"(o.hi), "+v"(o.mid), "+v"(o.lo), "+v"(r.hi), "+v"(r.mid), "+v"(r.lo));
+    asm("s_nop 2" : "+v"(o.hi), "+v"(o.mid), "+v"(o.lo));
 }
 
 // Operand of 4 complex legs (times sc, conjugated for the inverse trick) and
 // the operand of -i times the same legs.
-template <int MODE, bool CONJ>
+template <int MODE, bool CONJ, bool UNSCALED = false>
 __device__ __forceinline__ void make_operands(const float2 (&c)[4], const float (&sc)[4], MOp<MODE> &o,
                                               MOp<MODE> &r) {
   if constexpr (MODE == MODE_SPLIT_FP16) {
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       unsigned h, lo;
-      split_leg<CONJ>(c[l].x, c[l].y, sc[l], h, lo);
+      if constexpr (UNSCALED) split_leg1<CONJ>(c[l].x, c[l].y, h, lo);
+      else split_leg<CONJ>(c[l].x, c[l].y, sc[l], h, lo);
       o.hi[l] = h;
       o.lo[l] = lo;
-      r.hi[l] = rot_leg(h);
-      r.lo[l] = rot_leg(lo);
     }
+    // the products of o may start while the rotation is formed
+    operand_fence<MODE>(o);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      r.hi[l] = rot_leg(o.hi[l]);
+      r.lo[l] = rot_leg(o.lo[l]);
+    }
+    operand_fence<MODE>(r);
   } else {
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
@@ -186,14 +210,15 @@ __device__ __forceinline__ void make_operands(const float2 (&c)[4], const float 
       r.mid[l] = rm;
       r.lo[l] = rl;
     }
+    operand_fence<MODE>(o);
+    operand_fence<MODE>(r);
   }
-  operand_fence<MODE>(o, r);
 }
 template <int MODE, bool CONJ>
 __device__ __forceinline__ MOp<MODE> make_operand(const float2 (&c)[4]) {
   MOp<MODE> o, r;
   const float one[4] = {1.f, 1.f, 1.f, 1.f};
-  make_operands<MODE, CONJ>(c, one, o, r);
+  make_operands<MODE, CONJ, true>(c, one, o, r);
   return o;
 }
 
@@ -446,7 +471,7 @@ template <int L, int MODE> struct MfmaLine {
 #pragma unroll
     for (int cb = 0; cb < KB; ++cb) {
       MOp<MODE> y, yr;
-      make_operands<MODE, false>(x[cb], one, y, yr);
+      make_operands<MODE, false, true>(x[cb], one, y, yr);
       f4_t re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
       re = mprod<MODE, false>(y, w16, re);
       im = mprod<MODE, false>(yr, w16, im);
@@ -489,7 +514,7 @@ template <int L, int MODE> struct MfmaLine {
     MOp<MODE> d[KB], dr[KB];
     const float one[4] = {1.f, 1.f, 1.f, 1.f};
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) make_operands<MODE, true>(x[kb], one, d[kb], dr[kb]);
+    for (int kb = 0; kb < KB; ++kb) make_operands<MODE, true, true>(x[kb], one, d[kb], dr[kb]);
 #pragma unroll
     for (int rho = 0; rho < RZ; ++rho) {
       f4_t re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
