@@ -232,6 +232,24 @@ template <int L, int MODE> struct Direct {
   }
 };
 
+// The matrix-core engine reads its twiddles by index for every line; they
+// come from a copy of the length-L table in LDS, staged once per workgroup,
+// so the per-line lookups do not compete with the pass's HBM streams in the
+// vector memory pipeline.  (The float32 engine keeps each lane's twiddles in
+// registers.)
+template <int L, int MODE> struct TwiddleStage {
+  static constexpr bool ON = engine_kind<L, MODE>() == 2;
+  __device__ __forceinline__ static const float2 *stage(float2 *lds, const float2 *tab, int tid, int nt) {
+    if constexpr (ON) {
+      for (int n = tid; n < L; n += nt) lds[n] = tab[n];
+      __syncthreads();
+      return lds;
+    } else {
+      return tab;
+    }
+  }
+};
+
 // Non-temporal hints, chosen by measurement on the 512-length passes (whole
 // solve, 2.62k -> 2.68k solves/s): every store of a pass output streams, and
 // so do the tiled loads (128-byte row segments of W lines); contiguous line
@@ -333,7 +351,8 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2c_kernel(PassParams a) {
 
   float2 *wave_lines = smem + wave * LPW * C::SLOTS;
   LineEngine<L, MODE> eng;
-  eng.init(a.tw, lane);
+  __shared__ float2 tw_lds[TwiddleStage<L, MODE>::ON ? L : 1];
+  eng.init(TwiddleStage<L, MODE>::stage(tw_lds, a.tw, tid, NT), lane);
 
   using D = Direct<L, MODE>;
   TileRegs<ROWS_IN, W, NT, LD, float2> pf;
@@ -453,7 +472,8 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void r2c_kernel(PassParams a) {
 
   float2 *wave_lines = smem + wave * LPW * C::SLOTS;
   LineEngine<L, MODE> eng;
-  eng.init(a.tw, lane);
+  __shared__ float2 tw_lds[TwiddleStage<L, MODE>::ON ? L : 1];
+  eng.init(TwiddleStage<L, MODE>::stage(tw_lds, a.tw, tid, NT), lane);
 
   using D = Direct<L, MODE>;
   TileRegs<ROWS_IN, W, NT, LDR, float> pf;
@@ -585,7 +605,8 @@ __global__ __launch_bounds__((Geo<L, TS>::NT)) void c2r_kernel(PassParams a) {
 
   float2 *wave_lines = smem + wave * LPW * C::SLOTS;
   LineEngine<L, MODE> eng;
-  eng.init(a.tw, lane);
+  __shared__ float2 tw_lds[TwiddleStage<L, MODE>::ON ? L : 1];
+  eng.init(TwiddleStage<L, MODE>::stage(tw_lds, a.tw, tid, NT), lane);
 
   using D = Direct<L, MODE>;
   TileRegs<ROWS_IN, W, NT, LDC, float2> pf;
@@ -696,11 +717,15 @@ constexpr int kConvWaves = 4;
 // line of the array and stores nothing) so matrix-core stages always run on
 // whole wavefronts.  With one line per wavefront the walk is scalar.
 // 24-element lanes: two wavefronts per SIMD (see the single line buffer below)
-template <int L> constexpr int conv_min_waves() { return Shape<L>::E >= 24 ? 2 : 1; }
+// The fused fp16 matrix-core conv (one line per wavefront) is latency-bound:
+// keep it at four wavefronts per SIMD (128 registers; bf16 needs more).
+template <int L, int MODE> constexpr int conv_min_waves() {
+  return Shape<L>::E >= 24 ? 2 : (MODE == MODE_SPLIT_FP16 && engine_kind<L, MODE>() == 2 && kT<L> == 64) ? 4 : 1;
+}
 
 template <int L, bool PC, int MODE>
 __global__ __launch_bounds__(kConvWaves * 64)
-__attribute__((amdgpu_waves_per_eu(conv_min_waves<L>()))) void conv_kernel(ConvParams a) {
+__attribute__((amdgpu_waves_per_eu(conv_min_waves<L, MODE>()))) void conv_kernel(ConvParams a) {
   constexpr int E = Shape<L>::E, T = L / E, LPW = 64 / T, KR = L / 2 + 1;
   constexpr int SLOTS = line_lds_slots<L>();
   __shared__ float2 smem[kConvWaves * LPW * SLOTS];
@@ -710,11 +735,14 @@ __attribute__((amdgpu_waves_per_eu(conv_min_waves<L>()))) void conv_kernel(ConvP
   float2 *xch = smem + (wave * LPW + g) * SLOTS;
   float2 *wave_lines = smem + wave * LPW * SLOTS;
 
+  // (the table is staged before idle wavefronts leave: all reach the barrier)
+  __shared__ float2 tw_lds[TwiddleStage<L, MODE>::ON ? L : 1];
+  const float2 *tw = TwiddleStage<L, MODE>::stage(tw_lds, a.tw, tid, kConvWaves * 64);
   const int row0 = (block_order(a.xcd) * kConvWaves + wave) * LPW + g;
   if (!__any(row0 < a.nrows * a.nsolve)) return;  // whole wavefront idle
 
   LineEngine<L, MODE> eng;
-  eng.init(a.tw, lane);
+  eng.init(tw, lane);
 
   // rows are (solve, k_p, k_q') in mixed radix; walk them with carries
   const int stride = gridDim.x * kConvWaves * LPW;
