@@ -57,13 +57,18 @@ def solve_bytes(n, info, tile_sel):
     return float(sum(pass_bytes(n, info, plane=bool(tile_sel[2] & PLANE_BIT))))
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since it was taken."""
+TRAFFIC_SOURCES = ("paper_1211_5244_amd/csrc/passes.hip", "paper_1211_5244_amd/csrc/fft_core.h",
+                   "paper_1211_5244_amd/csrc/fft_mfma.h")
+
+
+def measured_traffic(kernel, mode="fp32"):
+    """HBM bytes per launch of pass `kernel` in precision `mode` (default tile
+    schedule) from the committed rocprofv3 counter summary, or None when the
+    kernel sources changed since it was taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in ("paper_1211_5244_amd/csrc/passes.hip", "paper_1211_5244_amd/csrc/fft_core.h"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     sha = h.hexdigest()[:16]
@@ -72,8 +77,8 @@ def measured_traffic(kernel):
         return None
     for line in open(path):
         parts = line.split()
-        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel:
-            fields = dict(p.split("=", 1) for p in parts[2:])
+        if len(parts) == 5 and parts[0] == "traffic" and parts[1] == kernel and parts[2] == mode:
+            fields = dict(p.split("=", 1) for p in parts[3:])
             if fields.get("source_sha") == sha:
                 return float(fields["bytes"])
     return None
@@ -241,6 +246,49 @@ def bench_host(torch, P, plan, r, count=20):
                           "pcie_gbs": nbytes / (t_pipe * 1e-3) / 1e9, "solves": count}}
 
 
+# The other configurations, timed in the default run as extra keys (tuned
+# FP32 and tuned split fp16): the four 128^3 BC classes and the 384-length
+# wire and surface grids.  Timing does not depend on the density's values,
+# so each solves a seeded normal field.
+EXTRA_WORKLOADS = ["free128", "wire128", "surface128", "periodic128",
+                   "wire192x192x384", "surface384x192x384"]
+
+
+def bench_workloads(torch, P, dev, steps, warmup):
+    from densities import WORKLOADS
+    stream = torch.cuda.current_stream(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(13)
+    out = {}
+    for name in EXTRA_WORKLOADS:
+        w = WORKLOADS[name]
+        n, bc = w["n"], w["bc"]
+        info = P.poisson_plan_describe(*n, bc)
+        r = torch.randn((n[2], n[1], n[0]), generator=g, device=dev, dtype=torch.float32)
+        V = torch.empty_like(r)
+        rec = {"n": list(n), "bc_mask": bc}
+        for prec, label in ((P.POISSON_FP32, "fp32"), (P.POISSON_SPLIT_FP16, "split_fp16")):
+            plan = P.Plan(n, bc, H, precision=prec)
+            plan.tune(r, V, stream=stream)
+            sel = plan.schedule[0]
+            for _ in range(warmup):
+                plan.solve(r, V, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                P.poisson_solve(plan.handle, r, V, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            b = solve_bytes(n, info, sel)
+            rec[label] = {"ms": ms, "solves_per_s": 1000.0 / ms, "alg_bytes": b,
+                          "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tile_schedule": list(sel)}
+            plan.close()
+        out[name] = rec
+        del r, V
+    return out
+
+
 class FullPaddedSolve:
     """The "3D FFT library" comparator of Section 4 and 5: a problem with
     free axes solved as a periodic problem on the whole padded grid S1 x S2
@@ -360,6 +408,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default schedules (short runs under a profiler)")
     ap.add_argument("--no-host", action="store_true", help="skip the host-buffer transfer rates")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other configurations and the Figure 1 rows")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy (counter calibration)")
     ap.add_argument("--fig1", action="store_true",
@@ -471,8 +521,8 @@ def main():
         "untuned_ms_per_step": untuned_ms,
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(names[dom]) if args.workload == "free256"
-                                 else None),
+                     "traffic": (measured_traffic(names[dom])
+                                 if args.workload == "free256" and not any(tile_sel) else None),
                      "alg_bytes_per_launch": pb[dom],
                      "launch_ms": per_pass[dom]},
         "solve_roofline": {"alg_bytes": alg_solve, "achieved": solve_gbs,
@@ -517,14 +567,25 @@ def main():
             sms = [float(np.mean([sev[k][j].elapsed_time(sev[k][j + 1]) for k in range(args.steps)]))
                    for j in range(len(sruns))]
             spb = pass_bytes(n, info, plane=len(sruns) == 3)
+            sdom = int(np.argmax(sms))
+            sname = sruns[sdom][0]
             out["split"][name] = {"ms_per_solve": t, "solves_per_s": 1000.0 / t,
                                   "solve_roofline_frac": solve_bytes(n, info, sp.schedule[0]) / (t * 1e-3) / 1e9
                                   / HBM_PEAK_GBS,
                                   "passes_ms": {nm: v for (nm, _, _), v in zip(sruns, sms)},
                                   "passes_frac": {nm: b / (v * 1e-3) / 1e9 / HBM_PEAK_GBS
                                                   for (nm, _, _), b, v in zip(sruns, spb, sms)},
+                                  "dominant": {"kernel": sname, "launch_ms": sms[sdom],
+                                               "alg_bytes_per_launch": spb[sdom],
+                                               "frac": spb[sdom] / (sms[sdom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                               "traffic": (measured_traffic(sname, name)
+                                                           if args.workload == "free256"
+                                                           and not any(sp.schedule[0]) else None)},
                                   "tile_schedule": list(sp.schedule[0]), "V": Vsplit}
             sp.close()
+    if not args.no_extra:
+        out["workloads"] = bench_workloads(torch, P, dev, steps=min(args.steps, 50), warmup=3)
+        out["fig1"] = fig1(torch, P, dev, steps=min(args.steps, 20), warmup=3)
     if not args.no_batch:
         out["batch"] = {"workload": "batch512 (edges 32..128, 4 BC classes, 4 Gaussians)",
                         "fp32": bench_batch(torch, P, dev),
