@@ -34,11 +34,11 @@
 //
 // Precision: each product is split so that float32 accuracy survives 16-bit
 // operands, with float32 accumulation.
-//   fp16: every block is scaled by one power of two so its largest value
+//   fp16: every line is scaled by one power of two so its largest value
 //         lies in [2^9, 2^10) (no factor then leaves the fp16 range), and
 //         x = hi + lo, W = Wh + Wl, D = Wh hi + Wh lo + Wl hi.  Keeping the
 //         values near 2^10 keeps lo in the normal range for everything
-//         within 12 binades of the block maximum; below that the error is
+//         within 12 binades of the line maximum; below that the error is
 //         under 2^-35 of the maximum.
 //   bf16: x = hi + mid + lo (three 8-bit mantissas), the same for W, and
 //         the six products of order >= 2^-16 are kept; bf16 has the float32
