@@ -23,3 +23,4 @@ from .greens import (  # noqa: F401
     padded_shape,
 )
 from .solve import brute_force, real_space_kernel, rel_l2, solve  # noqa: F401
+from . import isf  # noqa: F401
