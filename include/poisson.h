@@ -145,6 +145,20 @@ int poisson_kernel_set(poisson_plan_t plan, const double *kf_octant, int is_devi
  * with O(h^4) origin weights, then the DFT along the free axes. */
 int poisson_kernel_build(poisson_plan_t plan, void *stream);
 
+/* Build, in float64 on the device, the free-boundary Green's function of
+ * the BigDFT solver the paper implements (Sections 2-3 take their kernels
+ * from it) and set it as with poisson_kernel_set.  The grid values of the
+ * density are read as coefficients of Deslauriers-Dubuc interpolating
+ * scaling functions phi of even `order` (8..32; 16 is the usual choice), so
+ *   K(i) = -(h^2 / 4 pi) int phi(u1) phi(u2) phi(u3) / |i - u| d^3u,
+ * evaluated through the Gaussian integral of 1/r, which separates into 1-D
+ * projections of Gaussians onto phi and their DCTs (no 3-D transform).
+ * Fully free plans only (POISSON_E_UNSUPPORTED otherwise); an order out of
+ * range is POISSON_E_ARG.  Blocking: allocates a temporary device table of
+ * a few MB, enqueues the build on `stream`, waits for it and frees the
+ * table.  Solves see the new K^F afterwards. */
+int poisson_kernel_build_isf(poisson_plan_t plan, int order, void *stream);
+
 /* Copy the plan's float64 K^F octant to host memory (same layout as
  * poisson_kernel_set).  Synchronous. */
 int poisson_kernel_get(poisson_plan_t plan, double *kf_octant_host);

@@ -202,16 +202,20 @@ def isf_kernel_real(n, h, order=16, **quad):
     return -(h * h / (4.0 * math.pi)) * coulomb_integrals(order, shape, **quad)
 
 
-def isf_kernel_fourier(n, h, order=16, **quad):
-    """K^F of the fully free problem on the padded grid S_j = 2 N_j, shape
-    (S3, S2, S1), real float64: the even extension of the real-space octant
-    (K_pad[j] = K(min(j, S - j)) per axis) and its whole-grid FFT."""
+def isf_kernel_fourier(n, h, order=16, half=False, **quad):
+    """K^F of the fully free problem on the padded grid S_j = 2 N_j, real
+    float64: the even extension of the real-space octant (K_pad[j] =
+    K(min(j, S - j)) per axis) and its whole-grid FFT.  Shape (S3, S2, S1),
+    or with half=True the real-input half spectrum (S3, S2, S1/2+1), which is
+    all `solve` reads."""
     K = isf_kernel_real(n, h, order, **quad)
     S = tuple(2 * x for x in n)
     for axis, Sx in ((2, S[0]), (1, S[1]), (0, S[2])):
         j = np.arange(Sx)
         K = np.take(K, np.minimum(j, Sx - j), axis=axis)
-    kf = scipy.fft.fftn(K, workers=os.cpu_count() or 1)
+    fft = scipy.fft.rfftn if half else scipy.fft.fftn
+    kf = fft(K, workers=os.cpu_count() or 1)
+    del K
     if float(np.abs(kf.imag).max()) > 1e-9 * float(np.abs(kf.real).max()):
         raise AssertionError("kernel is not even: K^F has an imaginary part")
     return np.ascontiguousarray(kf.real)
@@ -220,5 +224,5 @@ def isf_kernel_fourier(n, h, order=16, **quad):
 def isf_kernel_octant(n, h, order=16, kf=None, **quad):
     """The unique octant 0 <= k_j <= S_j/2 of K^F (as greens.kernel_octant)."""
     if kf is None:
-        kf = isf_kernel_fourier(n, h, order, **quad)
+        kf = isf_kernel_fourier(n, h, order, half=True, **quad)
     return np.ascontiguousarray(kf[: n[2] + 1, : n[1] + 1, : n[0] + 1])

@@ -31,6 +31,7 @@ from ._lib import (  # noqa: F401
     poisson_batch_solve,
     poisson_batch_tune,
     poisson_kernel_build,
+    poisson_kernel_build_isf,
     poisson_kernel_get,
     poisson_kernel_set,
     poisson_last_error,
@@ -67,10 +68,12 @@ def _check_grid(t, n, what):
 class Plan:
     """One grid size, boundary-condition mask and spacing.
 
-    rho and V are float32 device tensors of shape (n3, n2, n1) (x fastest)."""
+    rho and V are float32 device tensors of shape (n3, n2, n1) (x fastest).
+    kernel="isf" builds the interpolating-scaling-function Green's function
+    of order isf_order instead of the default (fully free grids only)."""
 
     def __init__(self, n, bc_mask, h, precision=POISSON_FP32, build_kernel=True, stream=None,
-                 axis_order=None):
+                 axis_order=None, kernel="default", isf_order=16):
         self.n = tuple(int(v) for v in n)
         self.bc_mask = int(bc_mask)
         self.h = float(h)
@@ -81,7 +84,12 @@ class Plan:
             if stream is None:
                 import torch
                 stream = torch.cuda.current_stream()
-            poisson_kernel_build(self.handle, stream)
+            if kernel == "isf":
+                poisson_kernel_build_isf(self.handle, isf_order, stream)  # blocking
+            elif kernel == "default":
+                poisson_kernel_build(self.handle, stream)
+            else:
+                raise ValueError(f"unknown kernel {kernel!r}")
 
     @property
     def S(self):

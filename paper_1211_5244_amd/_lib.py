@@ -30,7 +30,8 @@ POISSON_FP32, POISSON_SPLIT_FP16, POISSON_SPLIT_BF16 = 0, 1, 2
 EXPORTED = (
     "poisson_plan", "poisson_plan_ordered", "poisson_plan_describe",
     "poisson_plan_describe_ordered", "poisson_plan_info", "poisson_plan_rows", "poisson_set_workspace",
-    "poisson_kernel_set", "poisson_kernel_build", "poisson_kernel_get", "poisson_solve",
+    "poisson_kernel_set", "poisson_kernel_build", "poisson_kernel_build_isf", "poisson_kernel_get",
+    "poisson_solve",
     "poisson_solve_passes", "poisson_solve_host", "poisson_solve_host_many",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
@@ -84,6 +85,7 @@ def load_library(path=None):
         "poisson_set_workspace": (_i, [_vp, _vp, _sz]),
         "poisson_kernel_set": (_i, [_vp, _vp, _i]),
         "poisson_kernel_build": (_i, [_vp, _vp]),
+        "poisson_kernel_build_isf": (_i, [_vp, _i, _vp]),
         "poisson_kernel_get": (_i, [_vp, _vp]),
         "poisson_solve": (_i, [_vp, _vp, _vp, _vp]),
         "poisson_solve_passes": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
@@ -212,6 +214,10 @@ def poisson_kernel_set(plan, kf_octant, is_device_ptr=None):
 
 def poisson_kernel_build(plan, stream=None):
     _check(load_library().poisson_kernel_build(plan, _stream(stream)))
+
+
+def poisson_kernel_build_isf(plan, order=16, stream=None):
+    _check(load_library().poisson_kernel_build_isf(plan, int(order), _stream(stream)))
 
 
 def poisson_kernel_get(plan, S):

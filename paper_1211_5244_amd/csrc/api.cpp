@@ -408,6 +408,33 @@ int poisson_kernel_build(poisson_plan_t P, void *stream) {
   return build_kernel_into(P, P->ws, P->ws ? P->g.ws_bytes : 0, static_cast<hipStream_t>(stream));
 }
 
+int poisson_kernel_build_isf(poisson_plan_t P, int order, void *stream) {
+  if (!P) return fail(POISSON_E_ARG, "plan is NULL");
+  if (order < 8 || order > 32 || order % 2)
+    return fail(POISSON_E_ARG, "interpolation order must be even, 8 to 32");
+  if (P->g.bc != 7u)
+    return fail(POISSON_E_UNSUPPORTED, "ISF kernels are built for fully free BCs only");
+  DeviceScope ds(P->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
+  int rc = ensure_workspace(P);  // as poisson_kernel_build: solves need it
+  if (rc) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bytes = psn::isf_table_bytes(P->g);
+  void *scratch = nullptr;
+  PSN_TRY_HIP(hipMalloc(&scratch, bytes), "hipMalloc(ISF tables)");
+  const double *tabs[3] = {P->cos_tab[0], P->cos_tab[1], P->cos_tab[2]};
+  hipError_t e = psn::launch_isf_build(P->g, P->h, order, P->kf64, scratch, bytes, tabs, s);
+  rc = e == hipSuccess ? finish_kernel(P, s) : hip_fail(e, "ISF K^F build");
+  if (rc == POISSON_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
+  (void)hipFree(scratch);
+  return rc;
+}
+
 int poisson_kernel_get(poisson_plan_t P, double *host) {
   if (!P || !host) return fail(POISSON_E_ARG, "NULL argument");
   if (!P->kernel_ready) return fail(POISSON_E_NO_KERNEL, "no K^F has been set or built");

@@ -23,6 +23,18 @@ struct PassIO {
 // One pass on `stream` for io.count solves: reads io.in[j], writes io.out[j]
 // (complex intermediates are float2, density and potential float).  `tw` is
 // the table exp(-2 pi i n / L), n = 0..L-1, of the pass's length; `kf` the
+// float64 K^F octant of the free-boundary Green's function on Deslauriers-
+// Dubuc interpolating scaling functions of even order 8..32 (fully free
+// geometries), written to `kf64`.  `scratch` (device, at least
+// isf_table_bytes(g)) holds the quadrature nodes and per-node DCT tables; the
+// node records are copied there with a blocking copy, the kernels are
+// enqueued on `stream`.  hipErrorInvalidValue for an order out of range or
+// too little scratch.
+size_t isf_table_bytes(const Geometry &g);
+hipError_t launch_isf_build(const Geometry &g, double h, int order, double *kf64, void *scratch,
+                            size_t scratch_bytes, const double *const cos_tabs[3],
+                            hipStream_t stream);
+
 // float32 K^F in pass order (conv pass only).  `mode` selects float32
 // radix stages (0) or split-precision matrix-core radix-8 stages (1: fp16
 // hi+lo, 2: bf16 three-way).  Returns a hipError_t.
@@ -58,6 +70,18 @@ hipError_t launch_plane_for_mode(const Geometry &g, const PassIO &io, const floa
 // cos_tabs[j]: device table cos(2 pi n / S_j), n = 0..S_j-1, for each axis.
 hipError_t launch_kernel_build(const Geometry &g, double h, double *kf64, double *tmp,
                                const double *const cos_tabs[3], hipStream_t stream);
+
+// float64 K^F octant of the free-boundary Green's function on Deslauriers-
+// Dubuc interpolating scaling functions of even order 8..32 (fully free
+// geometries), written to `kf64`.  `scratch` (device, at least
+// isf_table_bytes(g)) holds the quadrature nodes and per-node DCT tables; the
+// node records are copied there with a blocking copy, the kernels are
+// enqueued on `stream`.  hipErrorInvalidValue for an order out of range or
+// too little scratch.
+size_t isf_table_bytes(const Geometry &g);
+hipError_t launch_isf_build(const Geometry &g, double h, int order, double *kf64, void *scratch,
+                            size_t scratch_bytes, const double *const cos_tabs[3],
+                            hipStream_t stream);
 
 // float32 K^F in pass order [k_p][k_q'][k_r'] with 1/(S1 S2 S3) folded in,
 // from the float64 octant.

@@ -172,6 +172,7 @@ def test_null_and_bad_host_arguments():
     assert lib.poisson_plan(ctypes.byref(out), 8, 8, 8, 7, float("nan"), 0) == P._lib.POISSON_E_ARG
     assert lib.poisson_solve(None, None, None, None) == P._lib.POISSON_E_ARG
     assert lib.poisson_kernel_set(None, None, 0) == P._lib.POISSON_E_ARG
+    assert lib.poisson_kernel_build_isf(None, 16, None) == P._lib.POISSON_E_ARG
     assert lib.poisson_batch_create(ctypes.byref(out), 0, None, None, None, 0) == P._lib.POISSON_E_ARG
     assert lib.poisson_plan_destroy(None) == 0
 

@@ -216,6 +216,11 @@ def test_isf_kernel_fourier_is_real_even_and_octant_consistent():
         assert np.allclose(kf, np.take(kf, idx, axis=axis), rtol=0, atol=1e-12 * np.abs(kf).max())
     octant = isf.isf_kernel_octant(n, H, 16, kf=kf)
     assert octant.shape == (11, 9, 13)
+    # the half-spectrum route gives the same octant
+    half = isf.isf_kernel_fourier(n, H, 16, half=True)
+    assert half.shape == (20, 16, 13)
+    assert np.allclose(isf.isf_kernel_octant(n, H, 16), octant, rtol=0,
+                       atol=1e-13 * np.abs(octant).max())
     # k = 0 is the sum of the padded real-space kernel
     K = isf.isf_kernel_real(n, H, 16)
     w = [np.where((np.arange(o) == 0) | (np.arange(o) == o - 1), 1.0, 2.0) for o in K.shape]
