@@ -186,7 +186,15 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     torch.cuda.synchronize()
     t_graph = timed(g.replay)
     same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
-    # the autotuner: tile schedules per distinct plan, then the per-launch budget
+    # the same grouped launches on one stream (the default spreads them over
+    # four concurrent streams)
+    default_streams = B.streams
+    B.streams = 1
+    t_one_stream = timed(batched)
+    same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
+    B.streams = default_streams
+    # the autotuner: tile schedules per distinct plan, the per-launch budget,
+    # then the number of concurrent streams
     chunk_mb = B.tune(rhos, Vs)
     t_tuned = timed(batched)
     # tuned schedules may use the small-grid plane kernel, equal to float32 rounding only
@@ -205,8 +213,10 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     out = {"solves": len(items), "alg_bytes": alg, "alg_bytes_tuned": alg_tuned,
            "tuned_identical_to_loop": tuned_diff == 0.0,
            "untuned_identical_to_loop": bool(same),
-           "tuned_max_rel_l2_vs_loop": tuned_diff, "tuned_chunk_mb": chunk_mb}
+           "tuned_max_rel_l2_vs_loop": tuned_diff, "tuned_chunk_mb": chunk_mb,
+           "default_streams": default_streams, "tuned_streams": B.streams}
     for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph),
+                    ("batched_one_stream", t_one_stream),
                     ("batched_tuned", t_tuned), ("batched_tuned_graph", t_tuned_graph)):
         a = alg_tuned if "tuned" in name else alg
         out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),

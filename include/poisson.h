@@ -253,10 +253,8 @@ int poisson_batch_destroy(poisson_batch_t batch);
  * Bits 0-2 change which lines a workgroup transforms together, where it
  * runs and how long its HBM row segments are, never a line's arithmetic:
  * results are bitwise identical under all of them.  Bit 3 computes the same
- * butterflies in one kernel.  In float32 the compiler may order and contract
- * a few operations differently there: results then agree with the separate
- * passes to float32 rounding (relative L2 about 1e-7), not bitwise.  The
- * split modes fix their rounding order and stay bitwise equal. */
+ * butterflies in one kernel, with the rounding of every operation fixed in
+ * the source, so it is bitwise equal too, in every precision. */
 
 /* Set the five passes' schedules.  POISSON_E_ARG if one is outside 0..15,
  * POISSON_E_UNSUPPORTED if its tile width is not compiled for its pass
@@ -296,12 +294,28 @@ int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, i
 
 /* Autotuner for a batch: tunes each distinct plan's schedules on its
  * first chunk, then times whole batch solves for intermediates budgets of
- * 32..512 MiB and keeps the fastest (chunk_mb, may be NULL, receives it).
- * The arrays are those of poisson_batch_solve; V receives scratch values.
- * May reallocate the batch workspace (graphs captured before then must be
- * captured again).  reps <= 0 means 5.  Synchronous. */
+ * 32..512 MiB and keeps the fastest (chunk_mb, may be NULL, receives it),
+ * then the number of concurrent streams (1..4, poisson_batch_set_streams)
+ * at that budget.  The arrays are those of poisson_batch_solve; V receives
+ * scratch values.  May reallocate the batch workspace (graphs captured
+ * before then must be captured again).  reps <= 0 means 5.  Synchronous. */
 int poisson_batch_tune(poisson_batch_t batch, const float *const *rho_ptrs, float *const *V_ptrs,
                        int reps, double *chunk_mb, void *stream);
+
+/* Concurrent streams of a batch solve (1..4; 4 by default).  The batch's
+ * chunks (up to 64 solves of one distinct problem per launch) are spread
+ * over `streams` streams, largest first to the stream with the fewest
+ * algorithmic bytes so far: the caller's stream and streams-1 of the
+ * batch's own (default priority), forked from and joined back into the
+ * caller's stream with events, so a graph captured on the caller's stream
+ * holds them all.  Each stream has its own workspace region; a solve's
+ * result does not depend on its stream.  Kernels of different chunks then
+ * overlap, filling the ramp and tail of each launch (paper Section 5: many
+ * densities per run).  Creates the streams and events, may grow the
+ * workspace, and synchronizes the device: call it outside a capture.
+ * POISSON_E_ARG for streams outside 1..4. */
+int poisson_batch_set_streams(poisson_batch_t batch, int streams);
+int poisson_batch_get_streams(poisson_batch_t batch, int *streams);
 
 /* Residual check in float64 on the device: *out = ||v - ref||_2 / ||ref||_2
  * over `count` values, v float32 and ref float64, both device pointers.

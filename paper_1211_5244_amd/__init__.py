@@ -27,7 +27,9 @@ from ._lib import (  # noqa: F401
     poisson_batch_destroy,
     poisson_batch_kernel_build,
     poisson_batch_get_schedule,
+    poisson_batch_get_streams,
     poisson_batch_set_schedule,
+    poisson_batch_set_streams,
     poisson_batch_solve,
     poisson_batch_tune,
     poisson_kernel_build,
@@ -185,6 +187,15 @@ class Batch:
     def schedule(self, index):
         """The five pass schedules solve `index` runs with."""
         return poisson_batch_get_schedule(self.handle, index)
+
+    @property
+    def streams(self):
+        """Concurrent streams a batch solve uses (1..4)."""
+        return poisson_batch_get_streams(self.handle)
+
+    @streams.setter
+    def streams(self, k):
+        poisson_batch_set_streams(self.handle, k)
 
     def tune(self, rho_list, V_list, reps=0, stream=None):
         """Autotune tile schedules and the per-launch budget (V receives

@@ -36,7 +36,8 @@ EXPORTED = (
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
     "poisson_batch_set_schedule", "poisson_batch_get_schedule", "poisson_plan_get_schedule",
-    "poisson_plan_tune", "poisson_batch_tune", "poisson_rel_l2", "poisson_rel_l2_noalloc",
+    "poisson_plan_tune", "poisson_batch_tune", "poisson_batch_set_streams",
+    "poisson_batch_get_streams", "poisson_rel_l2", "poisson_rel_l2_noalloc",
     "poisson_last_error",
 )
 
@@ -104,6 +105,8 @@ def load_library(path=None):
         "poisson_plan_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
         "poisson_batch_tune": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                                     ctypes.POINTER(_d), _vp]),
+        "poisson_batch_set_streams": (_i, [_vp, _i]),
+        "poisson_batch_get_streams": (_i, [_vp, ctypes.POINTER(_i)]),
         "poisson_rel_l2": (_i, [_vp, _vp, _sz, ctypes.POINTER(_d), _vp]),
         "poisson_rel_l2_noalloc": (_i, [_vp, _vp, _sz, _vp, _vp]),
         "poisson_last_error": (ctypes.c_char_p, []),
@@ -317,6 +320,16 @@ def poisson_plan_tune(plan, rho, V, reps=0, stream=None):
     ms = (_d * 5)()
     _check(load_library().poisson_plan_tune(plan, _ptr(rho), _ptr(V), int(reps), ms, _stream(stream)))
     return tuple(ms)
+
+
+def poisson_batch_set_streams(batch, streams):
+    _check(load_library().poisson_batch_set_streams(batch, int(streams)))
+
+
+def poisson_batch_get_streams(batch):
+    out = _i()
+    _check(load_library().poisson_batch_get_streams(batch, ctypes.byref(out)))
+    return out.value
 
 
 def poisson_batch_tune(batch, rho_list, V_list, reps=0, stream=None):

@@ -190,6 +190,8 @@ def test_null_handles_of_the_later_entry_points():
     assert lib.poisson_solve_host(None, None, None, None) == E
     assert lib.poisson_solve_host_many(None, 1, None, None, None) == E
     assert lib.poisson_plan_info(None, None, None, None, None) == E
+    assert lib.poisson_batch_set_streams(None, 2) == E
+    assert lib.poisson_batch_get_streams(None, None) == E
     assert lib.poisson_rel_l2_noalloc(None, None, 0, None, None) == E
     assert lib.poisson_rel_l2_noalloc(None, None, 16, None, None) == E
     out = ctypes.c_void_p()

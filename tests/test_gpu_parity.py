@@ -591,3 +591,81 @@ def test_split_batch_equals_single_solves(torch_dev):
         # a line's place in its wavefront differs between a batched and a
         # lone solve; the result must not depend on it
         assert torch.equal(single, Vs[i]), (i, n, bc)
+
+
+def _all_edge_cases():
+    """Every edge of the mixed batch (32 to 128) in every BC class, two of
+    the smaller ones, so chunks hold several solves."""
+    from densities import BATCH_BCS, BATCH_EDGES
+    cases = []
+    i = 0
+    for e in BATCH_EDGES:
+        for bc in BATCH_BCS:
+            for _ in range(2 if e <= 64 else 1):
+                cases.append(((e, e, e), bc, 1300 + i))
+                i += 1
+    return cases
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP32, P.POISSON_SPLIT_FP16])
+def test_batch_all_edges_and_streams(torch_dev, precision):
+    """Edges 32..128 in all four classes: the batch on one stream and spread
+    over two and four concurrent streams gives the lone solves' results bit
+    for bit, and edges 96 and 128 of every class meet the oracle bar."""
+    torch = torch_dev
+    from densities import batch_density
+    cases = _all_edge_cases()
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    lone = []
+    for n, bc, _ in cases:
+        lone.append(P.Plan(n, bc, H, precision=precision).solve(rhos[len(lone)]))
+    torch.cuda.synchronize()
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases), precision=precision)
+    for streams in (1, 2, 4):
+        B.streams = streams
+        assert B.streams == streams
+        Vs = [torch.full_like(r, float("nan")) for r in rhos]
+        B.solve(rhos, Vs)
+        torch.cuda.synchronize()
+        for i, (n, bc, _) in enumerate(cases):
+            assert torch.equal(lone[i], Vs[i]), (streams, i, n, bc)
+    for i, (n, bc, _) in enumerate(cases):
+        if n[0] >= 96:
+            _check(Vs[i].cpu().numpy(), oracle.solve(rhos[i].cpu().numpy().astype(np.float64), bc, H),
+                   f"batch {n} bc={bc} precision={precision}")
+    with pytest.raises(P.PoissonError):
+        B.streams = 5
+    B.close()
+
+
+def test_batch_streams_graph_replay(torch_dev):
+    """A batch spread over three streams, captured on the caller's stream:
+    every replay (with eager work in between) equals the eager result."""
+    torch = torch_dev
+    from densities import batch_density
+    cases = _all_edge_cases()
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases))
+    B.streams = 3
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    eager = [v.clone() for v in Vs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in Vs:
+            v.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert torch.equal(Vs[i], eager[i]), (rep, i)
+        B.solve(rhos, Vs)
+        torch.cuda.synchronize()
+    B.close()
