@@ -224,6 +224,10 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n,
                          const unsigned *bc_mask, const double *h, int precision);
 /* Builds the default K^F of every distinct plan (as poisson_kernel_build). */
 int poisson_batch_kernel_build(poisson_batch_t batch, void *stream);
+/* Builds the ISF K^F of every distinct plan (as poisson_kernel_build_isf;
+ * blocking).  POISSON_E_UNSUPPORTED, before any build, if one of them is
+ * not fully free. */
+int poisson_batch_kernel_build_isf(poisson_batch_t batch, int order, void *stream);
 /* rho_ptrs / V_ptrs: host arrays of `count` device pointers, in creation
  * order; solve i may be in place (rho_ptrs[i] == V_ptrs[i]).  Asynchronous,
  * no allocation, no host sync: capturable into a HIP graph. */
@@ -291,6 +295,17 @@ int poisson_plan_get_schedule(poisson_plan_t plan, int tile_sel[5], int tile_lin
  * reps <= 0 means 10.  Needs K^F and a workspace; synchronous. */
 int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, int reps,
                       double pass_ms[5], void *stream);
+
+/* Tuned-schedule cache: a text file (path; NULL or "" switches it off)
+ * where poisson_plan_tune records the schedule it chose, one line per
+ * problem (n, bc_mask, precision, axis order) and device kind (arch name,
+ * compute units), replaced through a temporary file and a rename.  Plans
+ * created afterwards (poisson_plan, the plans of a batch) start from the
+ * cached schedule, so a process need not tune again.  The file is
+ * advisory: unreadable files, unknown lines and schedules this build does
+ * not compile are ignored.  Without a call, the environment variable
+ * POISSON_TUNE_CACHE gives the path.  Host only; returns POISSON_OK. */
+int poisson_set_tune_cache(const char *path);
 
 /* Autotuner for a batch: tunes each distinct plan's schedules on its
  * first chunk, then times whole batch solves for intermediates budgets of

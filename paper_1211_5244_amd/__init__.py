@@ -26,10 +26,12 @@ from ._lib import (  # noqa: F401
     poisson_batch_create,
     poisson_batch_destroy,
     poisson_batch_kernel_build,
+    poisson_batch_kernel_build_isf,
     poisson_batch_get_schedule,
     poisson_batch_get_streams,
     poisson_batch_set_schedule,
     poisson_batch_set_streams,
+    poisson_set_tune_cache,
     poisson_batch_solve,
     poisson_batch_tune,
     poisson_kernel_build,
@@ -163,13 +165,19 @@ class Plan:
 class Batch:
     """Many independent solves (sizes and BC masks may differ)."""
 
-    def __init__(self, n_list, bc_list, h_list, precision=POISSON_FP32, stream=None):
+    def __init__(self, n_list, bc_list, h_list, precision=POISSON_FP32, stream=None,
+                 kernel="default", isf_order=16):
         self.n_list = [tuple(int(v) for v in n) for n in n_list]
         self.handle = poisson_batch_create(self.n_list, list(bc_list), list(h_list), precision)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream()
-        poisson_batch_kernel_build(self.handle, stream)
+        if kernel == "isf":
+            poisson_batch_kernel_build_isf(self.handle, isf_order, stream)  # blocking
+        elif kernel == "default":
+            poisson_batch_kernel_build(self.handle, stream)
+        else:
+            raise ValueError(f"unknown kernel {kernel!r}")
 
     def solve(self, rho_list, V_list, stream=None):
         import torch

@@ -34,9 +34,10 @@ EXPORTED = (
     "poisson_solve",
     "poisson_solve_passes", "poisson_solve_host", "poisson_solve_host_many",
     "poisson_plan_destroy", "poisson_batch_create", "poisson_batch_kernel_build",
+    "poisson_batch_kernel_build_isf",
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
     "poisson_batch_set_schedule", "poisson_batch_get_schedule", "poisson_plan_get_schedule",
-    "poisson_plan_tune", "poisson_batch_tune", "poisson_batch_set_streams",
+    "poisson_plan_tune", "poisson_set_tune_cache", "poisson_batch_tune", "poisson_batch_set_streams",
     "poisson_batch_get_streams", "poisson_rel_l2", "poisson_rel_l2_noalloc",
     "poisson_last_error",
 )
@@ -105,6 +106,8 @@ def load_library(path=None):
         "poisson_plan_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
         "poisson_batch_tune": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                                     ctypes.POINTER(_d), _vp]),
+        "poisson_set_tune_cache": (_i, [ctypes.c_char_p]),
+        "poisson_batch_kernel_build_isf": (_i, [_vp, _i, _vp]),
         "poisson_batch_set_streams": (_i, [_vp, _i]),
         "poisson_batch_get_streams": (_i, [_vp, ctypes.POINTER(_i)]),
         "poisson_rel_l2": (_i, [_vp, _vp, _sz, ctypes.POINTER(_d), _vp]),
@@ -320,6 +323,15 @@ def poisson_plan_tune(plan, rho, V, reps=0, stream=None):
     ms = (_d * 5)()
     _check(load_library().poisson_plan_tune(plan, _ptr(rho), _ptr(V), int(reps), ms, _stream(stream)))
     return tuple(ms)
+
+
+def poisson_batch_kernel_build_isf(batch, order=16, stream=None):
+    _check(load_library().poisson_batch_kernel_build_isf(batch, int(order), _stream(stream)))
+
+
+def poisson_set_tune_cache(path):
+    """Tuned-schedule cache file (None switches it off)."""
+    _check(load_library().poisson_set_tune_cache(None if path is None else str(path).encode()))
 
 
 def poisson_batch_set_streams(batch, streams):

@@ -6,11 +6,16 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
+
+#include <unistd.h>
 
 #include "../../include/poisson.h"
 #include "kernels.h"
@@ -196,6 +201,41 @@ size_t batch_chunks(poisson_batch_t B, double budget_mb, std::vector<int> &chunk
   return ws;
 }
 
+// ------------------------------------------------ tuned-schedule cache
+// A text file of tuned schedules, one line per problem and device kind:
+//   v1 <arch> <CUs> <n1> <n2> <n3> <bc> <precision> <p> <q> <r> : <s1> .. <s5>
+// poisson_plan_tune writes its result there and new plans of the same
+// problem start from it, so a process need not tune again.  The file is
+// advisory: unreadable files, unknown lines and schedules this build does
+// not compile are ignored.
+std::mutex g_cache_mutex;
+std::string g_cache_path;
+bool g_cache_path_set = false;
+
+std::string cache_path_locked() {
+  if (!g_cache_path_set) {
+    g_cache_path_set = true;
+    if (const char *e = std::getenv("POISSON_TUNE_CACHE")) g_cache_path = e;
+  }
+  return g_cache_path;
+}
+
+std::string cache_key(const poisson_plan_s *P) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    cus = prop.multiProcessorCount;
+  }
+  std::ostringstream k;
+  k << "v1 " << arch << ' ' << cus << ' ' << P->g.n[0] << ' ' << P->g.n[1] << ' ' << P->g.n[2]
+    << ' ' << P->g.bc << ' ' << P->precision << ' ' << P->g.order[0] << ' ' << P->g.order[1]
+    << ' ' << P->g.order[2];
+  return k.str();
+}
+
 // Makes room for `lanes` workspace regions of `per_lane` bytes (waits for
 // stream s before replacing the allocation).  A failed allocation keeps the
 // old one.
@@ -241,6 +281,56 @@ bool schedule_valid(poisson_plan_t P, int k, int sched) {
     return (sched & 3) == 0 && (!(sched & psn::kPlaneBit) || psn::plane_available(P->g, P->precision));
   if (sched & psn::kPlaneBit) return false;
   return psn::pass_tile_lines(P->g.pass[k], sched, P->precision) > 0;
+}
+
+// Starts plan P from its cached schedule, if the cache has one this build
+// compiles.
+void cache_apply(poisson_plan_t P) {
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  const std::string path = cache_path_locked();
+  if (path.empty()) return;
+  std::ifstream in(path);
+  if (!in) return;
+  const std::string key = cache_key(P);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t colon = line.find(" : ");
+    if (colon == std::string::npos || line.compare(0, colon, key) != 0 || colon != key.size()) continue;
+    std::istringstream vals(line.substr(colon + 3));
+    int sel[5];
+    bool ok = true;
+    for (int k = 0; k < 5 && ok; ++k) ok = bool(vals >> sel[k]) && schedule_valid(P, k, sel[k]);
+    if (ok)
+      for (int k = 0; k < 5; ++k) P->g.pass[k].tile_sel = sel[k];
+  }
+}
+
+// Records plan P's schedule in the cache (replacing its line), through a
+// temporary file renamed over the old one.
+void cache_store(poisson_plan_t P) {
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  const std::string path = cache_path_locked();
+  if (path.empty()) return;
+  const std::string key = cache_key(P);
+  std::vector<std::string> keep;
+  {
+    std::ifstream in(path);
+    std::string line;
+    while (in && std::getline(in, line))
+      if (line.compare(0, key.size() + 3, key + " : ") != 0 && !line.empty()) keep.push_back(line);
+  }
+  std::ostringstream mine;
+  mine << key << " :";
+  for (int k = 0; k < 5; ++k) mine << ' ' << P->g.pass[k].tile_sel;
+  keep.push_back(mine.str());
+  const std::string tmp = path + ".tmp." + std::to_string(long(getpid()));
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return;
+    for (const std::string &l : keep) out << l << '\n';
+    if (!out) return;
+  }
+  (void)std::rename(tmp.c_str(), path.c_str());
 }
 
 int finish_kernel(poisson_plan_t P, hipStream_t s) {
@@ -385,6 +475,7 @@ int poisson_plan_ordered(poisson_plan_t *out, int n1, int n2, int n3, unsigned b
     P->kf64 = static_cast<double *>(p);
     if ((rc = plan_alloc(P, &p, sizeof(float) * g.kf_internal, "hipMalloc(K^F float32)"))) return cleanup(rc);
     P->kf32 = static_cast<float *>(p);
+    cache_apply(P);
     *out = P;
     return POISSON_OK;
   } catch (...) {
@@ -704,6 +795,21 @@ int poisson_batch_kernel_build(poisson_batch_t B, void *stream) {
   return POISSON_OK;
 }
 
+int poisson_batch_kernel_build_isf(poisson_batch_t B, int order, void *stream) {
+  if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  if (order < 8 || order > 32 || order % 2)
+    return fail(POISSON_E_ARG, "interpolation order must be even, 8 to 32");
+  for (size_t u = 0; u < B->plans.size(); ++u)
+    if (B->plans[u]->g.bc != 7u)
+      return fail(POISSON_E_UNSUPPORTED, "ISF kernels are built for fully free BCs only (distinct problem " +
+                                             std::to_string(u) + " is not)");
+  for (auto *P : B->plans) {
+    int rc = poisson_kernel_build_isf(P, order, stream);
+    if (rc) return rc;
+  }
+  return POISSON_OK;
+}
+
 int poisson_batch_solve(poisson_batch_t B, const float *const *rho, float *const *V, void *stream) {
   if (!B || !rho || !V) return fail(POISSON_E_ARG, "NULL argument");
   for (size_t i = 0; i < B->which.size(); ++i)
@@ -1003,7 +1109,16 @@ int poisson_plan_tune(poisson_plan_t P, const float *rho, float *V, int reps, do
   DeviceScope ds(P->device);
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
   if (reps <= 0) reps = 10;
-  return tune_plan_passes(P, 1, &rho, &V, P->ws, static_cast<hipStream_t>(stream), reps, pass_ms);
+  const int rc = tune_plan_passes(P, 1, &rho, &V, P->ws, static_cast<hipStream_t>(stream), reps, pass_ms);
+  if (rc == POISSON_OK) cache_store(P);
+  return rc;
+}
+
+int poisson_set_tune_cache(const char *path) {
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  g_cache_path_set = true;
+  g_cache_path = path ? path : "";
+  return POISSON_OK;
 }
 
 int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const *V, int reps,

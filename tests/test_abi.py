@@ -173,6 +173,7 @@ def test_null_and_bad_host_arguments():
     assert lib.poisson_solve(None, None, None, None) == P._lib.POISSON_E_ARG
     assert lib.poisson_kernel_set(None, None, 0) == P._lib.POISSON_E_ARG
     assert lib.poisson_kernel_build_isf(None, 16, None) == P._lib.POISSON_E_ARG
+    assert lib.poisson_batch_kernel_build_isf(None, 16, None) == P._lib.POISSON_E_ARG
     assert lib.poisson_batch_create(ctypes.byref(out), 0, None, None, None, 0) == P._lib.POISSON_E_ARG
     assert lib.poisson_plan_destroy(None) == 0
 
@@ -191,6 +192,7 @@ def test_null_handles_of_the_later_entry_points():
     assert lib.poisson_solve_host_many(None, 1, None, None, None) == E
     assert lib.poisson_plan_info(None, None, None, None, None) == E
     assert lib.poisson_batch_set_streams(None, 2) == E
+    assert lib.poisson_set_tune_cache(None) == 0  # host only: switches the cache off
     assert lib.poisson_batch_get_streams(None, None) == E
     assert lib.poisson_rel_l2_noalloc(None, None, 0, None, None) == E
     assert lib.poisson_rel_l2_noalloc(None, None, 16, None, None) == E

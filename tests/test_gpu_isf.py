@@ -140,3 +140,24 @@ def test_isf_rejections(torch_dev):
     torch.cuda.synchronize()
     assert np.array_equal(plan.kernel(), k0)
     plan.close()
+
+
+def test_isf_batch_equals_lone_solves(torch_dev):
+    """A batch of free problems with the ISF kernel gives the lone ISF
+    solves bit for bit; a batch with a non-free problem is refused before
+    any build."""
+    torch = torch_dev
+    cases = [(32, 32, 32), (48, 48, 48), (32, 32, 32), (24, 12, 16)]
+    rhos = [torch.from_numpy(_density(n, seed=880 + i)).cuda() for i, n in enumerate(cases)]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch(cases, [7] * len(cases), [H] * len(cases), kernel="isf")
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for i, n in enumerate(cases):
+        plan = P.Plan(n, 7, H, kernel="isf")
+        assert torch.equal(plan.solve(rhos[i]), Vs[i]), i
+        plan.close()
+    B.close()
+    with pytest.raises(P.PoissonError) as e:
+        P.Batch([(16, 16, 16), (16, 16, 16)], [7, 3], [H, H], kernel="isf")
+    assert e.value.code == P._lib.POISSON_E_UNSUPPORTED

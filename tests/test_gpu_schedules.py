@@ -321,3 +321,36 @@ def test_solve_passes_with_the_plane_bit(torch_dev):
     torch.cuda.synchronize()
     assert torch.equal(V, separate)
     assert torch.equal(separate, fused)  # fixed rounding: the same bits either way
+
+
+def test_tune_cache_round_trip(torch_dev, tmp_path):
+    """poisson_plan_tune records its schedule; new plans of the same problem
+    start from it (same results); unknown lines and schedules the build does
+    not compile are ignored."""
+    torch = torch_dev
+    path = tmp_path / "tuned.txt"
+    P.poisson_set_tune_cache(str(path))
+    try:
+        n, bc = (48, 24, 64), 3
+        r = _rho(torch, n, bc, seed=41)
+        plan = P.Plan(n, bc, H)
+        assert plan.schedule[0] == (0, 0, 0, 0, 0)  # nothing cached yet
+        ref = plan.solve(r).clone()
+        plan.tune(r)
+        tuned = plan.schedule[0]
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1, lines
+        key, vals = lines[0].split(" : ")
+        assert tuple(int(v) for v in vals.split()) == tuned
+        again = P.Plan(n, bc, H)
+        assert again.schedule[0] == tuned
+        assert torch.equal(again.solve(r), ref)
+        # other problems and precisions have their own lines
+        assert P.Plan(n, bc, H, precision=P.POISSON_SPLIT_FP16).schedule[0] == (0, 0, 0, 0, 0)
+        again.tune(r)
+        assert len(path.read_text().splitlines()) == 1  # replaced, not appended
+        path.write_text("not a cache line\n" + key + " : 3 3 3 3 3\n")
+        assert P.Plan(n, bc, H).schedule[0] == (0, 0, 0, 0, 0)
+    finally:
+        P.poisson_set_tune_cache(None)
+    assert P.Plan(n, bc, H).schedule[0] == (0, 0, 0, 0, 0)
