@@ -59,15 +59,17 @@ enum {
 
 enum { POISSON_FREE_X = 1, POISSON_FREE_Y = 2, POISSON_FREE_Z = 4 };
 
-/* Precision of the radix stages.  Data, twiddles, K^F and accumulation are
- * float32 in every mode.  The split modes compute each radix-8 stage as a
- * real 16x16 DFT matrix times 16 butterflies on the matrix cores, with the
- * butterflies scaled by a power of two per butterfly and split into 16-bit
- * parts whose cross products carry float32 accuracy. */
+/* Precision of the line transforms.  Data, twiddles, K^F and accumulation
+ * are float32 in every mode.  The split modes take a line of length
+ * L = 16 B (32..512) as two dense DFT factors (DFT_B and DFT_16, four-step
+ * form) on the matrix cores, with each line scaled by a power of two and
+ * split into 16-bit parts whose cross products carry float32 accuracy;
+ * lengths 768, 1024 and below 32 run their radix-8 stages as 16x16 DFT
+ * matrix products instead. */
 enum {
   POISSON_FP32 = 0,       /* all stages on the vector ALUs in float32 */
-  POISSON_SPLIT_FP16 = 1, /* radix-8 stages on MFMA: fp16 hi + lo, 3 products */
-  POISSON_SPLIT_BF16 = 2  /* radix-8 stages on MFMA: bf16 three-way split, 6 products */
+  POISSON_SPLIT_FP16 = 1, /* DFT products on MFMA: fp16 hi + lo, 3 products */
+  POISSON_SPLIT_BF16 = 2  /* DFT products on MFMA: bf16 three-way split, 6 products */
 };
 
 /* Create a plan for an n1 x n2 x n3 grid with spacing h (> 0, finite).
@@ -241,10 +243,9 @@ int poisson_batch_destroy(poisson_batch_t batch);
  * schedule 0..15 (0 is the default):
  *  - bits 0-1, tile width: passes 0, 1, 3 and 4 stage their lines through
  *    LDS in tiles of W consecutive lines, W about 16, 8, 4 or 32 complex
- *    lines for values 0..3.  Float32 mode compiles every width that fits
- *    the LDS of a compute unit and differs from a lower one; split modes
- *    compile width 0 only; pass 2 (the fused convolution) has no tile and
- *    takes width 0 only.
+ *    lines for values 0..3.  Every mode compiles every width that fits the
+ *    LDS of a compute unit and differs from a lower one; pass 2 (the fused
+ *    convolution) has no tile and takes width 0 only.
  *  - bit 2, workgroup order: 1 gives each of the chip's 8 XCDs (each with
  *    its own L2) a contiguous run of tiles (or kernel rows) per round
  *    instead of every eighth one.

@@ -95,8 +95,8 @@ template <int L, int TS> constexpr bool tile_distinct() {
            Geo<L, 3>::G != Geo<L, 2>::G;
 }
 
-// Complex lines per tile that schedule ts gives pass P at length L in float32
-// mode (0 if the schedule does not fit; split modes run schedule 0 only).
+// Complex lines per tile that schedule ts gives pass P at length L (0 if the
+// schedule does not fit).
 template <int L> int tile_lines_of(const Pass &P, int ts) {
   auto pick = [&](auto tsc) -> int {
     constexpr int T = decltype(tsc)::value;
@@ -950,11 +950,10 @@ hipError_t launch_c2r_ts(const Pass &P, const PassIO &io, const float2 *tw, hipS
   return hipGetLastError();
 }
 
-// The pass's tile schedule selects the kernel variant.  Only float32 mode
-// compiles the alternatives; a schedule that does not fit (or a split mode)
-// runs schedule 0.
+// The pass's tile schedule selects the kernel variant, in every precision; a
+// schedule that does not fit runs schedule 0.
 #define PSN_TILE_DISPATCH(LAUNCH, FITS, ...)                                   \
-  if constexpr (MODE == MODE_FP32) {                                           \
+  {                                                                            \
     switch (P.tile_sel & 3) {                                                  \
       case 1: if constexpr (FITS(1)) return LAUNCH<__VA_ARGS__, 1>(P, io, tw, s); break; \
       case 2: if constexpr (FITS(2)) return LAUNCH<__VA_ARGS__, 2>(P, io, tw, s); break; \
@@ -1245,7 +1244,6 @@ hipError_t launch_pass(const Pass &P, const PassIO &io, const float2 *tw, const 
 int pass_tile_lines(const Pass &P, int sched, int mode) {
   if (sched < 0 || sched >= kSchedules) return 0;
   const int ts = sched & 3;  // the XCD-order bit does not change the tile
-  if (mode != MODE_FP32 && ts != 0) return 0;
   switch (P.L) {
 #define PSN_CASE(LL) \
   case LL: return tile_lines_of<LL>(P, ts);

@@ -57,11 +57,15 @@ CASES = [((256, 256, 256), 7), ((24, 48, 12), 7), ((48, 24, 64), 3), ((12, 48, 2
          ((32, 24, 48), 0), ((96, 64, 48), 5)]
 
 
-@pytest.mark.parametrize("n,bc", CASES)
-def test_every_schedule_keeps_results(torch_dev, n, bc):
+SPLIT_CASES = [((256, 256, 256), 7, P.POISSON_SPLIT_FP16), ((48, 24, 64), 3, P.POISSON_SPLIT_FP16),
+               ((32, 24, 48), 0, P.POISSON_SPLIT_BF16), ((96, 64, 48), 5, P.POISSON_SPLIT_BF16)]
+
+
+@pytest.mark.parametrize("n,bc,precision", [(n, bc, P.POISSON_FP32) for n, bc in CASES] + SPLIT_CASES)
+def test_every_schedule_keeps_results(torch_dev, n, bc, precision):
     torch = torch_dev
     r = _rho(torch, n, bc, seed=700 + bc)
-    plan = P.Plan(n, bc, H)
+    plan = P.Plan(n, bc, H, precision=precision)
     ref = plan.solve(r).clone()
     compiled = _compiled(plan)
     print(f"{n} bc={bc}: compiled schedules per pass {compiled}", flush=True)
