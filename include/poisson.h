@@ -147,18 +147,25 @@ int poisson_kernel_set(poisson_plan_t plan, const double *kf_octant, int is_devi
  * with O(h^4) origin weights, then the DFT along the free axes. */
 int poisson_kernel_build(poisson_plan_t plan, void *stream);
 
-/* Build, in float64 on the device, the free-boundary Green's function of
- * the BigDFT solver the paper implements (Sections 2-3 take their kernels
- * from it) and set it as with poisson_kernel_set.  The grid values of the
- * density are read as coefficients of Deslauriers-Dubuc interpolating
- * scaling functions phi of even `order` (8..32; 16 is the usual choice), so
- *   K(i) = -(h^2 / 4 pi) int phi(u1) phi(u2) phi(u3) / |i - u| d^3u,
- * evaluated through the Gaussian integral of 1/r, which separates into 1-D
- * projections of Gaussians onto phi and their DCTs (no 3-D transform).
- * Fully free plans only (POISSON_E_UNSUPPORTED otherwise); an order out of
- * range is POISSON_E_ARG.  Blocking: allocates a temporary device table of
- * a few MB, enqueues the build on `stream`, waits for it and frees the
- * table.  Solves see the new K^F afterwards. */
+/* Build, in float64 on the device, the Green's function of the BigDFT
+ * solver the paper implements (Sections 2-3 take their kernels from it) and
+ * set it as with poisson_kernel_set.  Along the free axes the grid values
+ * of the density are read as coefficients of Deslauriers-Dubuc
+ * interpolating scaling functions phi of even `order` (8..32; 16 is the
+ * usual choice), and the Green's function is integrated against them:
+ *   free:     K(i) = -(h^2 / 4 pi) int phi3(u) / |i - u| d^3u;
+ *   surface:  h int phi(u) G_kappa(h (n - u)) du, G = -exp(-kappa|y|)/(2 kappa)
+ *             (|y|/2 at kappa = 0);
+ *   wire:     h^2 int phi2(u) G_kappa(h |n - u|) d^2u, G = -K0(kappa r)/(2 pi)
+ *             (ln(r)/(2 pi) at kappa = 0);
+ * with kappa^2 = sum of the periodic k_j^2, k_j = 2 pi f_j / (S_j h), as in
+ * poisson_kernel_build.  Each is evaluated through a Gaussian integral
+ * representation that separates into 1-D projections of Gaussians onto
+ * phi and their DCTs (no 3-D transform).  POISSON_E_UNSUPPORTED for a fully
+ * periodic plan; an order out of range is POISSON_E_ARG.  Blocking:
+ * allocates a temporary device table of a few MB, enqueues the build on
+ * `stream`, waits for it and frees the table.  Solves see the new K^F
+ * afterwards. */
 int poisson_kernel_build_isf(poisson_plan_t plan, int order, void *stream);
 
 /* Copy the plan's float64 K^F octant to host memory (same layout as
@@ -228,7 +235,7 @@ int poisson_batch_create(poisson_batch_t *out, int count, const int *n,
 int poisson_batch_kernel_build(poisson_batch_t batch, void *stream);
 /* Builds the ISF K^F of every distinct plan (as poisson_kernel_build_isf;
  * blocking).  POISSON_E_UNSUPPORTED, before any build, if one of them is
- * not fully free. */
+ * fully periodic. */
 int poisson_batch_kernel_build_isf(poisson_batch_t batch, int order, void *stream);
 /* rho_ptrs / V_ptrs: host arrays of `count` device pointers, in creation
  * order; solve i may be in place (rho_ptrs[i] == V_ptrs[i]).  Asynchronous,

@@ -226,3 +226,119 @@ def isf_kernel_octant(n, h, order=16, kf=None, **quad):
     if kf is None:
         kf = isf_kernel_fourier(n, h, order, half=True, **quad)
     return np.ascontiguousarray(kf[: n[2] + 1, : n[1] + 1, : n[0] + 1])
+
+
+# ------------------------------------------------------------ mixed BCs
+# Surface (one free axis) and wire (two free axes) problems: along the
+# periodic axes the kernel stays spectral, k_j = 2 pi f_j / (S_j h) and
+# kappa^2 = sum of periodic k_j^2 (the same reading as the sampled kernels),
+# and along the free axes the Green's function of (lap_d - kappa^2) is
+# integrated against the scaling functions, as in the free case:
+#   d = 1:  G(y) = -exp(-kappa |y|) / (2 kappa),  |y|/2 at kappa = 0;
+#   d = 2:  G(r) = -K0(kappa r) / (2 pi),          ln(r) / (2 pi) at kappa = 0,
+# K_kappa(n) = h^d int phi_d(u) G(h (n - u)) d^d u.  Gaussian integrals
+# separate them again (tau = h t, a = kappa h / 2):
+#   exp(-kappa|y|)/(2 kappa) = (1/(2 sqrt pi)) int exp(-y^2 t^2 - kappa^2/(4 t^2)) dt / t^2,
+#   |y|                      = (1/sqrt pi)     int (1 - exp(-y^2 t^2)) dt / t^2,
+#   K0(kappa r)              =                 int exp(-r^2 t^2 - kappa^2/(4 t^2)) dt / t,
+#   ln r                     =                 int (exp(-t^2) - exp(-r^2 t^2)) dt / t,
+# so with g(tau, n) of the free case
+#   d = 1, kappa > 0:  K = -(h^2 / (2 sqrt pi)) int g(tau, n) exp(-a^2/tau^2) dtau / tau^2
+#   d = 1, kappa = 0:  K =  (h^2 / (2 sqrt pi)) int (1 - g(tau, n)) dtau / tau^2
+#   d = 2, kappa > 0:  K = -(h^2 / (2 pi)) int g(tau, i) g(tau, j) exp(-a^2/tau^2) dtau / tau
+#   d = 2, kappa = 0:  K =  (h^2 / (2 pi)) [ln h + int (exp(-tau^2) - g(tau, i) g(tau, j)) dtau / tau].
+# Quadrature: the same Gauss-Legendre panels in ln tau, from MIXED_TAU_LO to
+# T_MAX; below, the integrands are their small-tau forms (n^2 tau_lo for
+# d = 1 at kappa = 0, negligible otherwise); above, only the origin keeps a
+# term (g ~ sqrt(pi)/tau there): -1/(4 T^2) times h^2 in every case, plus
+# h^2/(2 sqrt pi) / T for d = 1 at kappa = 0.  1 - g is formed as -expm1 where
+# g is the sample exp(-tau^2 n^2), so small tau loses nothing to cancellation.
+
+MIXED_TAU_LO = 1e-9
+
+
+def _free_kernel_1d(order, kappa_h, nfree, nodes):
+    """h^-2 K_kappa(n), n = 0 .. nfree, for one free axis."""
+    t, w, G, OneMinusG = nodes
+    n = np.arange(nfree + 1, dtype=np.float64)
+    c = 1.0 / (2.0 * math.sqrt(math.pi))
+    if kappa_h > 0.0:
+        a2 = (0.5 * kappa_h) ** 2
+        wk = w * np.exp(-a2 / t ** 2) / t ** 2
+        out = -c * (wk @ G[:, : nfree + 1])
+    else:
+        out = c * ((w / t ** 2) @ OneMinusG[:, : nfree + 1])
+        out += c * (n ** 2 * MIXED_TAU_LO + 1.0 / T_MAX)   # below the panels; above: the 1 of 1 - g
+        out[0] += c * (-math.sqrt(math.pi) / (2.0 * T_MAX ** 2))
+    out[0] += -0.25 / T_MAX ** 2 if kappa_h > 0.0 else 0.0
+    return out
+
+
+def _free_kernel_2d(order, kappa_h, n1, n2, h, nodes):
+    """h^-2 K_kappa(i, j), i = 0 .. n1 (fastest), j = 0 .. n2: shape (n2+1, n1+1)."""
+    t, w, G, _ = nodes
+    c = 1.0 / (2.0 * math.pi)
+    A, B = G[:, : n2 + 1], G[:, : n1 + 1]
+    if kappa_h > 0.0:
+        a2 = (0.5 * kappa_h) ** 2
+        wk = w * np.exp(-a2 / t ** 2) / t
+        out = -c * ((A * wk[:, None]).T @ B)
+    else:
+        const = math.log(h) + float(np.sum(w * np.exp(-t ** 2) / t))
+        out = c * (const - (A * (w / t)[:, None]).T @ B)
+    out[0, 0] += -0.25 / T_MAX ** 2
+    return out
+
+
+def _mixed_nodes(order, nmax):
+    t, w = quadrature_nodes(MIXED_TAU_LO, T_MAX, PANEL, GL_POINTS)
+    G = np.array([gauss_integrals(order, tq, nmax) for tq in t])
+    n = np.arange(nmax + 1, dtype=np.float64)
+    OneMinusG = np.array([-np.expm1(-(tq * n) ** 2) if dyadic_level(tq, order) == 0 else 1.0 - G[q]
+                          for q, tq in enumerate(t)])
+    return t, w, G, OneMinusG
+
+
+def isf_mixed_kernel_fourier(n, bc_mask, h, order=16, half=False):
+    """K^F for surface (one free axis) and wire (two free axes) problems on
+    the padded grid (S3, S2, S1) (half=True: the half spectrum along x): the
+    mixed representation (periodic axes in Fourier, free axes as the ISF
+    kernel at offsets min(j, S_j - j)), then the FFT along the free axes."""
+    if order not in ORDERS:
+        raise ValueError("interpolation order must be even, 8 to 32")
+    free = [j for j in range(3) if (bc_mask >> j) & 1]
+    per = [j for j in range(3) if not (bc_mask >> j) & 1]
+    if len(free) not in (1, 2):
+        raise ValueError("one or two free axes")
+    S = [n[j] * (2 if j in free else 1) for j in range(3)]
+    nodes = _mixed_nodes(order, max(n[j] for j in free))
+    # periodic wave numbers of every mode and the distinct kappa h values
+    ks = [2.0 * math.pi * np.fft.fftfreq(S[j], d=1.0 / S[j]) / (S[j] * h) for j in per]
+    grids = np.meshgrid(*ks, indexing="ij")
+    kappa_h = np.sqrt(sum(k ** 2 for k in grids)) * h
+    uniq, inv = np.unique(kappa_h, return_inverse=True)  # +-f give bitwise equal kappa
+    inv = inv.reshape(kappa_h.shape)
+    if len(free) == 1:
+        (f,) = free
+        tabs = np.array([_free_kernel_1d(order, float(kh), n[f], nodes) for kh in uniq])
+        idx = np.minimum(np.arange(S[f]), S[f] - np.arange(S[f]))
+        vals = h * h * tabs[:, idx]                     # (kappa, S_f)
+        mixed_pf = vals[inv]                            # (S_per0, S_per1, S_f)
+        order_axes = per + [f]
+    else:
+        f0, f1 = free
+        tabs = np.array([_free_kernel_2d(order, float(kh), n[f0], n[f1], h, nodes) for kh in uniq])
+        i0 = np.minimum(np.arange(S[f0]), S[f0] - np.arange(S[f0]))
+        i1 = np.minimum(np.arange(S[f1]), S[f1] - np.arange(S[f1]))
+        vals = h * h * tabs[:, i1][:, :, i0]            # (kappa, S_f1, S_f0)
+        mixed_pf = vals[inv]                            # (S_per, S_f1, S_f0)
+        order_axes = per + [f1, f0]
+    # to array axes (S3, S2, S1): physical axis j is array axis 2 - j
+    perm = [order_axes.index(j) for j in (2, 1, 0)]
+    mixed = np.transpose(mixed_pf, perm)
+    free_axes = tuple(2 - j for j in free)
+    kf = scipy.fft.fftn(mixed, axes=free_axes, workers=os.cpu_count() or 1)
+    if float(np.abs(kf.imag).max()) > 1e-9 * float(np.abs(kf.real).max()):
+        raise AssertionError("kernel is not even: K^F has an imaginary part")
+    kf = np.ascontiguousarray(kf.real)
+    return kf[:, :, : S[0] // 2 + 1].copy() if half else kf

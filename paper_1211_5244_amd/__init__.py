@@ -74,7 +74,7 @@ class Plan:
 
     rho and V are float32 device tensors of shape (n3, n2, n1) (x fastest).
     kernel="isf" builds the interpolating-scaling-function Green's function
-    of order isf_order instead of the default (fully free grids only)."""
+    of order isf_order instead of the default (grids with a free axis)."""
 
     def __init__(self, n, bc_mask, h, precision=POISSON_FP32, build_kernel=True, stream=None,
                  axis_order=None, kernel="default", isf_order=16):

@@ -547,8 +547,8 @@ int poisson_kernel_build_isf(poisson_plan_t P, int order, void *stream) {
   if (!P) return fail(POISSON_E_ARG, "plan is NULL");
   if (order < 8 || order > 32 || order % 2)
     return fail(POISSON_E_ARG, "interpolation order must be even, 8 to 32");
-  if (P->g.bc != 7u)
-    return fail(POISSON_E_UNSUPPORTED, "ISF kernels are built for fully free BCs only");
+  if ((P->g.bc & 7u) == 0u)
+    return fail(POISSON_E_UNSUPPORTED, "ISF kernels need at least one free axis");
   DeviceScope ds(P->device);
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the plan's device");
   int rc = ensure_workspace(P);  // as poisson_kernel_build: solves need it
@@ -800,9 +800,9 @@ int poisson_batch_kernel_build_isf(poisson_batch_t B, int order, void *stream) {
   if (order < 8 || order > 32 || order % 2)
     return fail(POISSON_E_ARG, "interpolation order must be even, 8 to 32");
   for (size_t u = 0; u < B->plans.size(); ++u)
-    if (B->plans[u]->g.bc != 7u)
-      return fail(POISSON_E_UNSUPPORTED, "ISF kernels are built for fully free BCs only (distinct problem " +
-                                             std::to_string(u) + " is not)");
+    if ((B->plans[u]->g.bc & 7u) == 0u)
+      return fail(POISSON_E_UNSUPPORTED, "ISF kernels need at least one free axis (distinct problem " +
+                                             std::to_string(u) + " is periodic)");
   for (auto *P : B->plans) {
     int rc = poisson_kernel_build_isf(P, order, stream);
     if (rc) return rc;

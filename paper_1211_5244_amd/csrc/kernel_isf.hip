@@ -51,6 +51,7 @@ constexpr int kIsfThreads = 256;
 struct IsfNode {
   double t;   // Gaussian parameter
   double w;   // quadrature weight, (2/sqrt(pi)) t dt/ds times the panel weight
+  double wt;  // the plain weight of dt (t dt/ds times the panel weight)
   int J;      // starting dyadic level (0: g is the sample exp(-t^2 n^2))
   int P;      // level-J samples kept for 0 <= p <= P
 };
@@ -60,7 +61,9 @@ struct IsfParams {
   int S[3];
   int m;                  // interpolation order
   int omax;               // max O_j
-  int row;                // O[0] + O[1] + O[2]: one node's DCT row
+  int row;                // one node's DCT row: O[0] + O[1] + O[2] (+ O[f1m])
+  int free_mask;          // axes whose DCT rows are made
+  int f1m;                // axis of the DCT of 1 - g (one free axis), else -1
   double a[kIsfMaxTaps];  // a_k at index k + m - 1
 };
 
@@ -139,6 +142,7 @@ std::vector<IsfNode> isf_nodes(int m) {
       IsfNode nd;
       nd.t = double(t);
       nd.w = double(two_over_sqrt_pi * t * w[i] * L / 2.0L);
+      nd.wt = double(t * w[i] * L / 2.0L);
       int J = 0;
       while (std::ldexp(1.0, J) < c * nd.t) ++J;
       nd.J = J;
@@ -196,15 +200,125 @@ __global__ __launch_bounds__(kIsfThreads) void isf_table_kernel(IsfParams p, con
   for (int d = 0; d < 3; ++d) {
     const int O = p.O[d], S = p.S[d];
     const int top = min(R, O - 1);
+    if ((p.free_mask >> d) & 1) {
+      for (int k = tid; k < O; k += kIsfThreads) {
+        double acc = 0.0;
+        for (int n = 0; n <= top; ++n) {
+          const double wn = (n == 0 || 2 * n == S) ? 1.0 : 2.0;
+          acc += wn * g[n] * cs[d][(long long)k * n % S];
+        }
+        row[off + k] = acc;
+      }
+    }
+    off += O;
+  }
+  if (p.f1m >= 0) {
+    // the DCT of 1 - g along the one free axis: g is 0 past R, and where g
+    // is the sample exp(-t^2 n^2), 1 - g is -expm1(-t^2 n^2) (no cancellation)
+    const int d = p.f1m, O = p.O[d], S = p.S[d];
     for (int k = tid; k < O; k += kIsfThreads) {
       double acc = 0.0;
-      for (int n = 0; n <= top; ++n) {
+      for (int n = 0; n < O; ++n) {
         const double wn = (n == 0 || 2 * n == S) ? 1.0 : 2.0;
-        acc += wn * g[n] * cs[d][(long long)k * n % S];
+        const double x = nd.t * n;
+        const double omg = nd.J == 0 ? -expm1(-x * x) : (n <= R ? 1.0 - g[n] : 1.0);
+        acc += wn * omg * cs[d][(long long)k * n % S];
       }
       row[off + k] = acc;
     }
-    off += O;
+  }
+}
+
+// Surface and wire problems: one workgroup per periodic wave-number pair
+// (surface) or wave number (wire), kappa^2 the sum of the periodic k_j^2,
+// k_j = 2 pi f_j / (S_j h), a = kappa h / 2.  Along the free axes
+//   surface, kappa > 0: -(h^2 / (2 sqrt pi)) int DCT g(t) exp(-a^2/t^2) dt / t^2
+//   surface, kappa = 0:  (h^2 / (2 sqrt pi)) int DCT (1 - g(t)) dt / t^2
+//   wire, kappa > 0:    -(h^2 / (2 pi)) int DCT g(t) DCT g(t) exp(-a^2/t^2) dt / t
+//   wire, kappa = 0:     (h^2 / (2 pi)) [(ln h + int exp(-t^2) dt / t) prod S_f at k = 0
+//                                        - int DCT g(t) DCT g(t) dt / t]
+// (the transforms of the ISF integrals of exp(-kappa|y|)/(2 kappa), |y|/2,
+// K0(kappa r)/(2 pi) and ln(r)/(2 pi)), plus the end pieces: -h^2/(4 T^2)
+// from the origin above T in every case; for the surface at kappa = 0 also
+// the 1 of 1 - g above T (S_f / T at k = 0) and below the panels
+// (t_min DCT(n^2)).  The node weights of the workgroup's kappa sit in LDS.
+constexpr int kIsfMaxNodes = 1024;
+__global__ __launch_bounds__(kIsfThreads) void isf_assemble_mixed_kernel(
+    IsfParams p, const IsfNode *nodes, int count, const double *table, double h,
+    double wire_const, const double *dct_n2, double *out) {
+  __shared__ double wk[kIsfMaxNodes];
+  const double pi = 3.14159265358979323846;
+  int fr[2], nf = 0, per[2], np = 0;
+  for (int d = 0; d < 3; ++d) {
+    if ((p.free_mask >> d) & 1) fr[nf++] = d;
+    else per[np++] = d;
+  }
+  // this workgroup's periodic octant indices
+  int kp[2] = {0, 0};
+  {
+    int b = blockIdx.x;
+    for (int i = 0; i < np; ++i) {
+      kp[i] = b % p.O[per[i]];
+      b /= p.O[per[i]];
+    }
+  }
+  double kappa2 = 0.0;
+  for (int i = 0; i < np; ++i) {
+    const double k = 2.0 * pi * kp[i] / (p.S[per[i]] * h);
+    kappa2 += k * k;
+  }
+  const double a2 = 0.25 * kappa2 * h * h;
+  const bool zero = kappa2 == 0.0;
+  for (int q = threadIdx.x; q < count; q += kIsfThreads) {
+    const double t = nodes[q].t, wt = nodes[q].wt;
+    if (nf == 1) wk[q] = zero ? wt / (t * t) : wt * exp(-a2 / (t * t)) / (t * t);
+    else wk[q] = zero ? wt / t : wt * exp(-a2 / (t * t)) / t;
+  }
+  __syncthreads();
+  const double Tm = kIsfTMax;
+  long long stride[3] = {1, p.O[0], (long long)p.O[0] * p.O[1]};
+  long long base = 0;
+  for (int i = 0; i < np; ++i) base += kp[i] * stride[per[i]];
+  int off[3];
+  off[0] = 0;
+  off[1] = p.O[0];
+  off[2] = p.O[0] + p.O[1];
+  const int extra = p.O[0] + p.O[1] + p.O[2];
+  if (nf == 1) {
+    const int f = fr[0], O = p.O[f];
+    const double c = h * h / (2.0 * sqrt(pi));
+    for (int k = threadIdx.x; k < O; k += kIsfThreads) {
+      double acc = 0.0;
+      if (zero) {
+        for (int q = 0; q < count; ++q) acc += wk[q] * table[(size_t)q * p.row + extra + k];
+        acc += kIsfTMin * dct_n2[k];
+        if (k == 0) acc += double(p.S[f]) / Tm;
+        acc = c * acc;
+      } else {
+        for (int q = 0; q < count; ++q) acc += wk[q] * table[(size_t)q * p.row + off[f] + k];
+        acc = -c * acc;
+      }
+      out[base + k * stride[f]] = acc - h * h / (4.0 * Tm * Tm);
+    }
+  } else {
+    const int f0 = fr[0], f1 = fr[1], O0 = p.O[f0], O1 = p.O[f1];
+    const double c = h * h / (2.0 * pi);
+    for (int e = threadIdx.x; e < O0 * O1; e += kIsfThreads) {
+      const int k0 = e % O0, k1 = e / O0;
+      double acc = 0.0;
+      for (int q = 0; q < count; ++q) {
+        const double *row = table + (size_t)q * p.row;
+        acc += wk[q] * row[off[f0] + k0] * row[off[f1] + k1];
+      }
+      if (zero) {
+        acc = -acc;
+        if (e == 0) acc += wire_const * double(p.S[f0]) * double(p.S[f1]);
+        acc = c * acc;
+      } else {
+        acc = -c * acc;
+      }
+      out[base + k0 * stride[f0] + k1 * stride[f1]] = acc - h * h / (4.0 * Tm * Tm);
+    }
   }
 }
 
@@ -235,10 +349,14 @@ __global__ void isf_assemble_kernel(IsfParams p, const IsfNode *nodes, int count
 
 size_t isf_table_bytes(const Geometry &g) {
   const size_t nodes = isf_nodes(16).size();
-  size_t row = 0;
-  for (int j = 0; j < 3; ++j) row += size_t(g.S[j] / 2 + 1);
-  // the node records, then the DCT rows
-  return nodes * sizeof(IsfNode) + 256 + nodes * row * sizeof(double);
+  size_t row = 0, omax = 0;
+  for (int j = 0; j < 3; ++j) {
+    row += size_t(g.S[j] / 2 + 1);
+    omax = std::max(omax, size_t(g.S[j] / 2 + 1));
+  }
+  row += omax;  // the DCT of 1 - g (one free axis)
+  // the node records, the DCT of n^2, then the DCT rows
+  return nodes * sizeof(IsfNode) + 256 + omax * sizeof(double) + 256 + nodes * row * sizeof(double);
 }
 
 hipError_t launch_isf_build(const Geometry &g, double h, int order, double *kf64, void *scratch,
@@ -246,32 +364,73 @@ hipError_t launch_isf_build(const Geometry &g, double h, int order, double *kf64
                             hipStream_t s) {
   if (order < 8 || order > 32 || order % 2 || scratch_bytes < isf_table_bytes(g))
     return hipErrorInvalidValue;
+  const unsigned fm = g.bc & 7u;
+  const int nfree = int(fm & 1u) + int((fm >> 1) & 1u) + int((fm >> 2) & 1u);
+  if (nfree == 0) return hipErrorInvalidValue;
   IsfParams p;
   p.m = order;
   p.omax = 0;
   p.row = 0;
+  p.free_mask = int(fm);
+  p.f1m = -1;
   for (int j = 0; j < 3; ++j) {
     p.S[j] = g.S[j];
     p.O[j] = g.S[j] / 2 + 1;
     p.omax = std::max(p.omax, p.O[j]);
     p.row += p.O[j];
+    if (nfree == 1 && ((fm >> j) & 1u)) p.f1m = j;
   }
+  if (p.f1m >= 0) p.row += p.O[p.f1m];
   if (p.omax > kIsfBuf) return hipErrorInvalidValue;
   dd_filter(order, p.a);
   const std::vector<IsfNode> nodes = isf_nodes(order);
+  if (int(nodes.size()) > kIsfMaxNodes) return hipErrorInvalidValue;
   for (const IsfNode &nd : nodes)
     if (nd.P >= kIsfBuf) return hipErrorInvalidValue;
-  IsfNode *dnodes = static_cast<IsfNode *>(scratch);
+  char *base = static_cast<char *>(scratch);
+  IsfNode *dnodes = reinterpret_cast<IsfNode *>(base);
   const size_t node_bytes = (nodes.size() * sizeof(IsfNode) + 255) / 256 * 256;
-  double *table = reinterpret_cast<double *>(static_cast<char *>(scratch) + node_bytes);
-  // a blocking copy: `nodes` lives on this function's stack
+  double *dct_n2 = reinterpret_cast<double *>(base + node_bytes);
+  const size_t n2_bytes = (size_t(p.omax) * sizeof(double) + 255) / 256 * 256;
+  double *table = reinterpret_cast<double *>(base + node_bytes + n2_bytes);
+  // blocking copies: the host arrays live on this function's stack
   hipError_t e = hipMemcpy(dnodes, nodes.data(), nodes.size() * sizeof(IsfNode),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
+  if (p.f1m >= 0) {
+    // DCT-I of n^2 along the free axis (the small-t piece of the surface
+    // kernel at kappa = 0), in long double
+    const int f = p.f1m, O = p.O[f], S = p.S[f];
+    std::vector<double> v(O);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < O; ++k) {
+      long double acc = 0.0L;
+      for (int n = 0; n < O; ++n) {
+        const long double wn = (n == 0 || 2 * n == S) ? 1.0L : 2.0L;
+        acc += wn * (long double)n * n * cosl(two_pi * (long double)((long long)k * n % S) / S);
+      }
+      v[k] = double(acc);
+    }
+    e = hipMemcpy(dct_n2, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(isf_table_kernel, dim3(unsigned(nodes.size())), dim3(kIsfThreads), 0, s, p,
                      (const IsfNode *)dnodes, cos_tabs[0], cos_tabs[1], cos_tabs[2], table);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (nfree < 3) {
+    // one workgroup per periodic octant index (pair)
+    long long groups = 1;
+    long double wire_const = logl((long double)h);
+    for (int j = 0; j < 3; ++j)
+      if (!((fm >> j) & 1u)) groups *= p.O[j];
+    for (const IsfNode &nd : nodes)
+      wire_const += (long double)nd.wt * expl(-(long double)nd.t * nd.t) / nd.t;
+    hipLaunchKernelGGL(isf_assemble_mixed_kernel, dim3(unsigned(groups)), dim3(kIsfThreads), 0, s,
+                       p, (const IsfNode *)dnodes, int(nodes.size()), (const double *)table, h,
+                       double(wire_const), (const double *)dct_n2, kf64);
+    return hipGetLastError();
+  }
   const double pi = 3.14159265358979323846;
   const double pref = -(h * h) / (4.0 * pi);
   const double tail_all = pi / (kIsfTMax * kIsfTMax);

@@ -1,8 +1,8 @@
-"""GPU parity of the interpolating-scaling-function (ISF) Green's function
-(free BCs): the float64 builder against the oracle's K^F (a different
-discretization of the same integral: real-space kernel and FFT there,
-separable DCT sums here), and ISF solves against the oracle's solve with that
-kernel, in every precision."""
+"""GPU parity of the interpolating-scaling-function (ISF) Green's functions
+(free, surface and wire BCs): the float64 builder against the oracle's K^F (a
+different discretization of the same integrals: real-space kernel and FFT
+there, separable DCT sums here), and ISF solves against the oracle's solve
+with that kernel, in every precision."""
 
 import math
 
@@ -119,7 +119,7 @@ def test_isf_gaussian_potential_on_the_gpu(torch_dev):
 
 
 def test_isf_rejections(torch_dev):
-    plan = P.Plan((16, 16, 16), 3, H)  # wire: not fully free
+    plan = P.Plan((16, 16, 16), 0, H)  # fully periodic: no free axis
     with pytest.raises(P.PoissonError) as e:
         P.poisson_kernel_build_isf(plan.handle, 16)
     assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
@@ -159,5 +159,94 @@ def test_isf_batch_equals_lone_solves(torch_dev):
         plan.close()
     B.close()
     with pytest.raises(P.PoissonError) as e:
-        P.Batch([(16, 16, 16), (16, 16, 16)], [7, 3], [H, H], kernel="isf")
+        P.Batch([(16, 16, 16), (16, 16, 16)], [7, 0], [H, H], kernel="isf")
     assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
+
+
+
+def _mixed_kf_error(n, bc, order):
+    plan = P.Plan(n, bc, H, kernel="isf", isf_order=order)
+    kf = plan.kernel()
+    plan.close()
+    S = [n[j] * (2 if (bc >> j) & 1 else 1) for j in range(3)]
+    ref = isf.isf_mixed_kernel_fourier(n, bc, H, order, half=True)[: S[2] // 2 + 1, : S[1] // 2 + 1, :]
+    d = float(np.max(np.abs(kf - ref)) / np.max(np.abs(ref)))
+    print(f"ISF K^F {n} bc={bc} order {order}: {d:.2e}", flush=True)
+    return d
+
+
+@pytest.mark.parametrize("n,bc,order", [((8, 12, 6), 2, 16), ((12, 8, 16), 3, 16), ((16, 8, 8), 1, 8),
+                                        ((8, 16, 12), 5, 32), ((16, 16, 16), 6, 12),
+                                        ((32, 24, 48), 4, 16), ((24, 48, 32), 3, 20)])
+def test_isf_mixed_kernel_matches_oracle(torch_dev, n, bc, order):
+    assert _mixed_kf_error(n, bc, order) <= KF_REL
+
+
+@pytest.mark.parametrize("n,bc", [((192, 192, 384), 3), ((384, 192, 384), 2)])
+def test_isf_mixed_kernel_full_size(torch_dev, n, bc):
+    """The 384-length wire and surface grids."""
+    assert _mixed_kf_error(n, bc, 16) <= KF_REL
+
+
+def _mixed_density(n, bc, seed):
+    gs = draw_gaussians(n, H, 6, (1.0, 3.0), seed)
+    return gaussian_mixture(n, bc, H, gs).astype(np.float32)
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP32, P.POISSON_SPLIT_FP16, P.POISSON_SPLIT_BF16])
+@pytest.mark.parametrize("n,bc", [((32, 24, 48), 2), ((48, 32, 24), 3), ((24, 48, 32), 5)])
+def test_isf_mixed_solve_matches_oracle(torch_dev, n, bc, precision):
+    torch = torch_dev
+    rho = _mixed_density(n, bc, seed=910 + bc)
+    kf = isf.isf_mixed_kernel_fourier(n, bc, H, 16, half=True)
+    ref = oracle.solve(rho.astype(np.float64), bc, H, kf=kf)
+    plan = P.Plan(n, bc, H, precision=precision, kernel="isf")
+    V = plan.solve(torch.from_numpy(rho).cuda())
+    torch.cuda.synchronize()
+    _check(V.cpu().numpy(), ref, f"ISF {n} bc={bc} prec {precision}")
+    plan.close()
+
+
+def test_isf_surface_high_mode_on_the_gpu(torch_dev):
+    """Physics through the HIP path: a sheet modulated at kappa h = 0.98
+    (surface, y free) is solved to float32 level with the ISF kernel, about
+    a thousand times better than with the sampled kernel."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from closed_forms import gaussian1, grid_axes, sheet_potential
+    torch = torch_dev
+    N = 32
+    n = (N, N, N)
+    x, y, z = grid_axes(n, H)
+    L = N * H
+    k = 2 * math.pi * 5 / L
+    rho = (np.cos(k * x)[None, None, :] * gaussian1(y, 0.5 * L, 0.9)[None, :, None]
+           * np.ones((N, 1, 1))).astype(np.float32)
+    want = (np.cos(k * x)[None, None, :] * sheet_potential(y, 0.5 * L, 0.9, k)[None, :, None]
+            * np.ones((N, 1, 1)))
+    errs = []
+    for kernel in ("isf", "default"):
+        plan = P.Plan(n, 2, H, kernel=kernel)
+        V = plan.solve(torch.from_numpy(rho).cuda())
+        torch.cuda.synchronize()
+        errs.append(oracle.rel_l2(V.cpu().numpy(), want))
+        plan.close()
+    print(f"surface kappa h = 0.98: ISF {errs[0]:.2e}, sampled kernel {errs[1]:.2e}", flush=True)
+    assert errs[0] <= 1e-6
+    assert errs[0] * 100 <= errs[1]
+
+
+def test_isf_mixed_batch_equals_lone_solves(torch_dev):
+    torch = torch_dev
+    cases = [((32, 32, 32), 2), ((32, 32, 32), 3), ((48, 48, 48), 7), ((32, 32, 32), 2), ((24, 48, 32), 5)]
+    rhos = [torch.from_numpy(_mixed_density(n, bc, seed=990 + i)).cuda() for i, (n, bc) in enumerate(cases)]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch([c[0] for c in cases], [c[1] for c in cases], [H] * len(cases), kernel="isf")
+    B.solve(rhos, Vs)
+    torch.cuda.synchronize()
+    for i, (n, bc) in enumerate(cases):
+        plan = P.Plan(n, bc, H, kernel="isf")
+        assert torch.equal(plan.solve(rhos[i]), Vs[i]), i
+        plan.close()
+    B.close()

@@ -226,3 +226,110 @@ def test_isf_kernel_fourier_is_real_even_and_octant_consistent():
     w = [np.where((np.arange(o) == 0) | (np.arange(o) == o - 1), 1.0, 2.0) for o in K.shape]
     total = np.einsum("cba,c,b,a->", K, w[0], w[1], w[2])
     assert abs(octant[0, 0, 0] - total) <= 1e-12 * abs(total)
+
+
+# ------------------------------------------------------------ mixed BCs
+import sys as _sys
+_sys.path.insert(0, __import__("os").path.dirname(__file__))
+from closed_forms import (gaussian1, grid_axes, line_potential_kappa,  # noqa: E402
+                          line_potential_kappa0, mesh, sheet_potential)
+
+
+def _surface_case(N, a, kernel):
+    h = H * 32 / N
+    n = (N, N, N)
+    x, y, z = grid_axes(n, h)
+    L = N * h
+    k = 2 * math.pi * a / L
+    rho = np.cos(k * x)[None, None, :] * gaussian1(y, 0.5 * L, 0.9)[None, :, None] * np.ones((N, 1, 1))
+    want = (np.cos(k * x)[None, None, :] * sheet_potential(y, 0.5 * L, 0.9, k)[None, :, None]
+            * np.ones((N, 1, 1)))
+    kf = isf.isf_mixed_kernel_fourier(n, 2, h, 16, half=True) if kernel == "isf" else None
+    return oracle.rel_l2(oracle.solve(rho, 2, h, kf=kf), want)
+
+
+def _wire_case(N, mode, kernel):
+    h = H * 32 / N
+    n = (N, N, N)
+    X, Y, Z = mesh(n, h)
+    L = N * h
+    r = np.sqrt((X - L / 2) ** 2 + (Y - L / 2) ** 2)
+    g2 = np.exp(-r ** 2 / (2 * 0.81)) / (2 * math.pi * 0.81)
+    if mode == 0:
+        rho, want = g2, line_potential_kappa0(r, 0.9)
+    else:
+        k = 2 * math.pi * mode / L
+        rho = np.cos(k * Z) * g2
+        want = np.cos(k * Z) * line_potential_kappa(r[0], 0.9, k)[None]
+    kf = isf.isf_mixed_kernel_fourier(n, 3, h, 16, half=True) if kernel == "isf" else None
+    return oracle.rel_l2(oracle.solve(rho, 3, h, kf=kf), want)
+
+
+@pytest.mark.parametrize("a", [0, 1, 5])
+def test_isf_surface_sheet_potential(a):
+    """Surface BCs (y free): cos(2 pi a x/L) g(y) against the closed form.
+    The ISF kernel stays at the 1e-7 level up to the high mode a = 5 (kappa h
+    = 0.98), where the sampled kernel's small-kappa h origin weight leaves
+    about 1e-3."""
+    e16, e32 = _surface_case(16, a, "isf"), _surface_case(32, a, "isf")
+    assert e32 <= 4e-7, (a, e32)
+    assert e16 / e32 >= 4, (a, e16, e32)
+    assert _surface_case(32, a, "sampled") >= 10 * e32
+
+
+@pytest.mark.parametrize("mode", [0, 1, 4])
+def test_isf_wire_line_potential(mode):
+    """Wire BCs (z periodic): a Gaussian line charge, uniform (kappa = 0) or
+    cos-modulated up to kappa h = 0.79, against the radial closed forms."""
+    e16, e32 = _wire_case(16, mode, "isf"), _wire_case(32, mode, "isf")
+    assert e32 <= 4e-7, (mode, e32)
+    assert e16 / e32 >= 4, (mode, e16, e32)
+    assert _wire_case(32, mode, "sampled") >= 10 * e32
+
+
+def test_isf_surface_kappa0_far_field_exact():
+    """|y|/2 against phi: int phi(u) |n - u| du = |n| exactly once the
+    support of phi lies on one side of n (phi's first moment vanishes)."""
+    nodes = isf._mixed_nodes(16, 40)
+    K = isf._free_kernel_1d(16, 0.0, 40, nodes)
+    n = np.arange(41)
+    far = n >= 15
+    assert np.max(np.abs(K[far] - 0.5 * n[far]) / (0.5 * n[far])) <= 1e-13
+    # and the kappa > 0 kernel tends to the sampled -exp(-kappa h n)/(2 kappa h)
+    kh = 0.05
+    Kk = isf._free_kernel_1d(16, kh, 40, nodes)
+    want = -np.exp(-kh * n) / (2 * kh)
+    assert np.max(np.abs(Kk[far] - want[far]) / np.abs(want[far])) <= 1e-12
+
+
+def test_isf_wire_kappa0_far_field():
+    nodes = isf._mixed_nodes(16, 40)
+    K = isf._free_kernel_2d(16, 0.0, 40, 40, H, nodes)
+    for i, j in ((40, 0), (30, 30), (25, 36)):
+        r = math.hypot(i, j)
+        want = (math.log(H) + math.log(r)) / (2 * math.pi)
+        assert abs(K[j, i] - want) <= 1e-12 * abs(want), (i, j)
+
+
+@pytest.mark.parametrize("bc", [2, 3, 5])
+def test_isf_mixed_quadrature_split_points(bc):
+    """Moving the lower end of the panels, raising the cut-off or halving
+    the panels leaves the mixed K^F unchanged to rounding."""
+    n = (8, 12, 6)
+    base = isf.isf_mixed_kernel_fourier(n, bc, H, 16)
+    scale = np.abs(base).max()
+    for attr, val in (("MIXED_TAU_LO", 1e-11), ("T_MAX", 16384.0), ("PANEL", 0.5)):
+        old = getattr(isf, attr)
+        setattr(isf, attr, val)
+        try:
+            other = isf.isf_mixed_kernel_fourier(n, bc, H, 16)
+        finally:
+            setattr(isf, attr, old)
+        assert np.max(np.abs(other - base)) <= 1e-12 * scale, attr
+
+
+def test_isf_mixed_rejects_free_and_periodic():
+    with pytest.raises(ValueError):
+        isf.isf_mixed_kernel_fourier((8, 8, 8), 7, H)
+    with pytest.raises(ValueError):
+        isf.isf_mixed_kernel_fourier((8, 8, 8), 0, H)
