@@ -310,7 +310,7 @@ int poisson_plan_tune(poisson_plan_t plan, const float *rho_dev, float *V_dev, i
  * compute units), replaced through a temporary file and a rename.  Plans
  * created afterwards (poisson_plan, the plans of a batch) start from the
  * cached schedule, so a process need not tune again.  The file is
- * advisory: unreadable files, unknown lines and schedules this build does
+ * advisory: unreadable files, unknown lines and schedules the library does
  * not compile are ignored.  Without a call, the environment variable
  * POISSON_TUNE_CACHE gives the path.  Host only; returns POISSON_OK. */
 int poisson_set_tune_cache(const char *path);

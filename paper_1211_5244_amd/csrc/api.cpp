@@ -206,7 +206,7 @@ size_t batch_chunks(poisson_batch_t B, double budget_mb, std::vector<int> &chunk
 //   v1 <arch> <CUs> <n1> <n2> <n3> <bc> <precision> <p> <q> <r> : <s1> .. <s5>
 // poisson_plan_tune writes its result there and new plans of the same
 // problem start from it, so a process need not tune again.  The file is
-// advisory: unreadable files, unknown lines and schedules this build does
+// advisory: unreadable files, unknown lines and schedules the library does
 // not compile are ignored.
 std::mutex g_cache_mutex;
 std::string g_cache_path;
@@ -283,7 +283,7 @@ bool schedule_valid(poisson_plan_t P, int k, int sched) {
   return psn::pass_tile_lines(P->g.pass[k], sched, P->precision) > 0;
 }
 
-// Starts plan P from its cached schedule, if the cache has one this build
+// Starts plan P from its cached schedule, if the cache has one the library
 // compiles.
 void cache_apply(poisson_plan_t P) {
   std::lock_guard<std::mutex> lock(g_cache_mutex);
