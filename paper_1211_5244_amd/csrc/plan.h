@@ -63,8 +63,10 @@ double algorithmic_bytes(const int n[3], const int S[3], const int order[3]);
 // periodic, r free), lengths up to 128.
 #define PSN_PLANE_CASES(X)                                                      \
   X(32, 32, false, false) X(48, 48, false, false) X(64, 64, false, false)       \
+  X(96, 96, false, false) X(128, 128, false, false)                             \
   X(64, 64, true, true) X(96, 96, true, true) X(128, 128, true, true)          \
-  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)
+  X(32, 64, false, true) X(48, 96, false, true) X(64, 128, false, true)        \
+  X(96, 192, false, true) X(128, 256, false, true)
 
 // Whether geometry g can run passes 1-3 as the plane kernel: a compiled
 // (L_q, L_r) case whose q-lines are contiguous in A1 and are written back

@@ -96,7 +96,8 @@ def test_every_schedule_keeps_results(torch_dev, n, bc, precision):
 # every compiled plane-kernel geometry: periodic, free, wire and surface cubes
 PLANE_CASES = [((32, 32, 32), 0), ((48, 48, 48), 0), ((64, 64, 64), 0), ((32, 32, 32), 7),
                ((32, 32, 32), 3), ((48, 48, 48), 7), ((64, 64, 64), 7), ((32, 32, 32), 2),
-               ((48, 48, 48), 2), ((64, 64, 64), 2)]
+               ((48, 48, 48), 2), ((64, 64, 64), 2), ((96, 96, 96), 0), ((128, 128, 128), 0),
+               ((96, 96, 96), 2), ((128, 128, 128), 2)]
 
 
 @pytest.mark.parametrize("n,bc", PLANE_CASES)
@@ -142,7 +143,8 @@ def test_plane_kernel_matches_three_passes(torch_dev, n, bc):
 
 @pytest.mark.parametrize("precision", [P.POISSON_SPLIT_FP16, P.POISSON_SPLIT_BF16])
 @pytest.mark.parametrize("n,bc", [((32, 32, 32), 7), ((48, 48, 48), 0), ((64, 64, 64), 2),
-                                  ((32, 32, 32), 3), ((64, 64, 64), 7)])
+                                  ((32, 32, 32), 3), ((64, 64, 64), 7), ((128, 128, 128), 0),
+                                  ((96, 96, 96), 2)])
 def test_split_plane_kernel_equals_three_passes(torch_dev, n, bc, precision):
     """The plane kernel in the split modes.  The split line transform fixes
     its rounding order (matrix-core products, twiddle products with a fixed

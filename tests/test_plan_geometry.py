@@ -160,6 +160,7 @@ def test_plane_cases_of_the_gpu_tests_are_enabled(dump):
     """Every geometry the GPU plane-kernel test selects has the kernel."""
     for n, bc in [((32, 32, 32), 0), ((48, 48, 48), 0), ((64, 64, 64), 0), ((32, 32, 32), 7),
                   ((32, 32, 32), 3), ((48, 48, 48), 7), ((64, 64, 64), 7), ((32, 32, 32), 2),
-                  ((48, 48, 48), 2), ((64, 64, 64), 2)]:
+                  ((48, 48, 48), 2), ((64, 64, 64), 2), ((96, 96, 96), 0), ((128, 128, 128), 0),
+                  ((96, 96, 96), 2), ((128, 128, 128), 2)]:
         g, passes = dump(n, bc)
         assert _plane_ok(g, passes), (n, bc)
