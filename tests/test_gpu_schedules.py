@@ -220,10 +220,10 @@ def test_schedule_rejects_bad_values(torch_dev):
     assert list(plan.schedule[0]) == [0] * 5  # unchanged after a rejected call
     split = P.Plan((32, 32, 32), 7, H, precision=P.POISSON_SPLIT_FP16)
     with pytest.raises(P.PoissonError) as e:
-        split.set_schedule([1, 0, 0, 0, 0])
+        split.set_schedule([0, 0, 1, 0, 0])  # the conv pass has no tile width
     assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
-    split.set_schedule([4] * 5)  # width 0 in XCD order is compiled for split modes
-    assert list(split.schedule[0]) == [4] * 5
+    split.set_schedule([5, 4, 4, 4, 5])  # split modes compile the tile widths too
+    assert list(split.schedule[0]) == [5, 4, 4, 4, 5]
 
 
 @pytest.mark.parametrize("n,bc", [((256, 256, 256), 7), ((64, 96, 48), 3)])
