@@ -62,9 +62,9 @@ TRAFFIC_SOURCES = ("paper_1211_5244_amd/csrc/passes.hip", "paper_1211_5244_amd/c
 
 
 def measured_traffic(kernel, mode="fp32"):
-    """HBM bytes per launch of pass `kernel` in precision `mode` (default tile
-    schedule) from the committed rocprofv3 counter summary, or None when the
-    kernel sources changed since it was taken."""
+    """HBM bytes per launch of pass `kernel` in precision `mode` (that pass on
+    its default tile schedule) from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since it was taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
@@ -556,7 +556,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(names[dom])
-                                 if args.workload == "free256" and not any(tile_sel) else None),
+                                 if args.workload == "free256" and tile_sel[runs[dom][1]] == 0
+                                 and runs[dom][1] == runs[dom][2] else None),
                      "alg_bytes_per_launch": pb[dom],
                      "launch_ms": per_pass[dom]},
         "solve_roofline": {"alg_bytes": alg_solve, "achieved": solve_gbs,
@@ -614,7 +615,9 @@ def main():
                                                "frac": spb[sdom] / (sms[sdom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                                "traffic": (measured_traffic(sname, name)
                                                            if args.workload == "free256"
-                                                           and not any(sp.schedule[0]) else None)},
+                                                           and sp.schedule[0][sruns[sdom][1]] == 0
+                                                           and sruns[sdom][1] == sruns[sdom][2]
+                                                           else None)},
                                   "tile_schedule": list(sp.schedule[0]), "V": Vsplit}
             sp.close()
     if not args.no_extra:
