@@ -43,7 +43,7 @@ def _kf_error(n, order):
 
 @pytest.mark.parametrize("n,order", [((8, 8, 8), 16), ((12, 8, 6), 16), ((16, 16, 16), 8),
                                      ((6, 12, 24), 32), ((32, 24, 48), 16), ((6, 64, 4), 20),
-                                     ((48, 48, 48), 12)])
+                                     ((48, 48, 48), 12), ((2, 4, 2), 16), ((2, 2, 2), 32)])
 def test_isf_kernel_matches_oracle(torch_dev, n, order):
     assert _kf_error(n, order) <= KF_REL
 
@@ -177,7 +177,8 @@ def _mixed_kf_error(n, bc, order):
 
 @pytest.mark.parametrize("n,bc,order", [((8, 12, 6), 2, 16), ((12, 8, 16), 3, 16), ((16, 8, 8), 1, 8),
                                         ((8, 16, 12), 5, 32), ((16, 16, 16), 6, 12),
-                                        ((32, 24, 48), 4, 16), ((24, 48, 32), 3, 20)])
+                                        ((32, 24, 48), 4, 16), ((24, 48, 32), 3, 20),
+                                        ((2, 4, 4), 2, 16), ((2, 2, 4), 3, 16)])
 def test_isf_mixed_kernel_matches_oracle(torch_dev, n, bc, order):
     assert _mixed_kf_error(n, bc, order) <= KF_REL
 
