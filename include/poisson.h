@@ -246,8 +246,9 @@ int poisson_batch_destroy(poisson_batch_t batch);
 
 /* Schedules and the autotuner.
  *
- * The radix decomposition of each FFT length is fixed.  Each pass has a
- * schedule 0..15 (0 is the default):
+ * The grouped launches fix the radix decomposition of each FFT length (the
+ * persistent schedule below tunes it).  Each pass has a schedule 0..15 (0
+ * is the default):
  *  - bits 0-1, tile width: passes 0, 1, 3 and 4 stage their lines through
  *    LDS in tiles of W consecutive lines, W about 16, 8, 4 or 32 complex
  *    lines for values 0..3.  Every mode compiles every width that fits the
@@ -319,7 +320,11 @@ int poisson_set_tune_cache(const char *path);
  * first chunk, then times whole batch solves for intermediates budgets of
  * 32..512 MiB and keeps the fastest (chunk_mb, may be NULL, receives it),
  * then the number of concurrent streams (1..4, poisson_batch_set_streams)
- * at that budget.  The arrays are those of poisson_batch_solve; V receives
+ * at that budget.  A float32 batch then times the persistent schedule
+ * (radix choice per line length, then items of 64, 256 or 1024 KiB) and
+ * keeps it as the batch's mode only if it beats the grouped launches
+ * (poisson_batch_get_mode tells which).  The arrays are those of
+ * poisson_batch_solve; V receives
  * scratch values.  May reallocate the batch workspace (graphs captured
  * before then must be captured again).  reps <= 0 means 5.  Synchronous. */
 int poisson_batch_tune(poisson_batch_t batch, const float *const *rho_ptrs, float *const *V_ptrs,
@@ -339,6 +344,69 @@ int poisson_batch_tune(poisson_batch_t batch, const float *const *rho_ptrs, floa
  * POISSON_E_ARG for streams outside 1..4. */
 int poisson_batch_set_streams(poisson_batch_t batch, int streams);
 int poisson_batch_get_streams(poisson_batch_t batch, int *streams);
+
+/* The persistent schedule of a batch (paper Section 5: many densities per
+ * run; each item runs a piece of one pass of Section 3).  With
+ * POISSON_BATCH_QUEUE, poisson_batch_solve is ONE kernel launch: a fixed
+ * grid of workgroups (as many as fit the device at once) takes work items
+ * from a device queue that holds every (solve, pass) segment in pass order
+ * (all pass-0 segments, then all pass-1 segments, ...), and an item of
+ * pass k > 0 waits until every item of pass k - 1 of its solve is
+ * complete.  Completion is counted per (solve, pass) and per pass level;
+ * each wait is bounded (poisson_batch_set_queue_spin) and a wait that runs
+ * out sets a sticky flag (poisson_batch_queue_status) instead of hanging.
+ * The line transforms are generic in length: a tile of complex lines in LDS
+ * and one Stockham step per radix (2, 3, 4, 8) in the order the radix
+ * choice gives; float32 arithmetic, with the rounding of every operation
+ * fixed, so a solve's result depends only on its radix choices and tile
+ * shape, not on the batch it runs in.  Float32 batches only.  Every solve
+ * gets its own intermediates (the sum of the distinct plans' workspaces
+ * over all solves, allocated at the first queue solve after a change).  The
+ * first queue solve after creation, a schedule change or with new arrays
+ * uploads descriptors (blocking, outside graph capture: a capture then
+ * fails with POISSON_E_STATE); later ones with the same arrays are a single
+ * asynchronous launch and capturable.  Calls that overlap on one batch
+ * race on its counters. */
+#define POISSON_BATCH_GROUPED 0 /* per-pass launches of chunks over streams (default) */
+#define POISSON_BATCH_QUEUE 1   /* one persistent launch over a work queue */
+/* POISSON_E_UNSUPPORTED for POISSON_BATCH_QUEUE on a split-precision batch. */
+int poisson_batch_set_mode(poisson_batch_t batch, int mode);
+int poisson_batch_get_mode(poisson_batch_t batch, int *mode);
+/* Radix decomposition of a length-L queue transform for choice `radix_sel`:
+ * 0 radix-8 stages first (then 4 or 2, then 3), 1 radix-4 stages (then 2,
+ * then 3), 2 the stages of choice 0 in reverse order.  Writes the radices,
+ * first stage first, and returns their count; POISSON_E_UNSUPPORTED for a
+ * length outside the library's set, POISSON_E_ARG for another choice.  Host
+ * only. */
+int poisson_queue_radices(int length, int radix_sel, int radices[12]);
+/* Radix choice of every queue transform of length `length` in this batch
+ * (0 by default; poisson_batch_tune picks them). */
+int poisson_batch_set_queue_radix(poisson_batch_t batch, int length, int radix_sel);
+int poisson_batch_get_queue_radix(poisson_batch_t batch, int length, int *radix_sel);
+/* Tile of the queue transforms: tile_elems complex elements (power of two,
+ * 64..2048; default 2048) hold tile_elems / L lines of length L (at least
+ * one); an item is as many tiles as carry about item_kb KiB in and out
+ * (default 256). */
+int poisson_batch_set_queue_shape(poisson_batch_t batch, int tile_elems, int item_kb);
+/* Spin limit of every queue wait (default 2^20 polls, on the order of a
+ * second; > 0). */
+int poisson_batch_set_queue_spin(poisson_batch_t batch, unsigned spin_limit);
+/* Waits for the device, then returns and clears the batch's sticky queue
+ * flags: bit 0 = a wait ran out (the results of the solve it belonged to
+ * are undefined). */
+int poisson_batch_queue_status(poisson_batch_t batch, unsigned *flags);
+/* Host simulation of the queue protocol (no GPU): `workers` threads play
+ * workgroups over (solve, pass) segments of seg_items[pass * nsolve +
+ * solve] items (each >= 1), with the device kernel's queue order, release
+ * and wait rules, and check that no item passed its wait before every item
+ * of its dependency had finished its work, that every item ran once and
+ * that the counters end at zero.  fault plants a protocol mistake for tests
+ * of these checks: 1 releases held lower-level items after a wait instead
+ * of before it, 2 counts an item complete before its work.  stats (may be
+ * NULL) receives waits, releases, violations and waits that ran out.
+ * POISSON_E_STATE if a check fails. */
+int poisson_queue_simulate(int nsolve, const int *seg_items, int workers, int fault,
+                           unsigned seed, long long stats[4]);
 
 /* Residual check in float64 on the device: *out = ||v - ref||_2 / ||ref||_2
  * over `count` values, v float32 and ref float64, both device pointers.

@@ -13,6 +13,8 @@ from __future__ import annotations
 from ._lib import (  # noqa: F401
     EXPORTED,
     LIB_PATH,
+    POISSON_BATCH_GROUPED,
+    POISSON_BATCH_QUEUE,
     POISSON_FP32,
     POISSON_FREE_X,
     POISSON_FREE_Y,
@@ -27,8 +29,17 @@ from ._lib import (  # noqa: F401
     poisson_batch_destroy,
     poisson_batch_kernel_build,
     poisson_batch_kernel_build_isf,
+    poisson_batch_get_mode,
+    poisson_batch_get_queue_radix,
     poisson_batch_get_schedule,
     poisson_batch_get_streams,
+    poisson_batch_queue_status,
+    poisson_batch_set_mode,
+    poisson_batch_set_queue_radix,
+    poisson_batch_set_queue_shape,
+    poisson_batch_set_queue_spin,
+    poisson_queue_radices,
+    poisson_queue_simulate,
     poisson_batch_set_schedule,
     poisson_batch_set_streams,
     poisson_set_tune_cache,
@@ -204,6 +215,32 @@ class Batch:
     @streams.setter
     def streams(self, k):
         poisson_batch_set_streams(self.handle, k)
+
+    @property
+    def mode(self):
+        """POISSON_BATCH_GROUPED (per-pass launches) or POISSON_BATCH_QUEUE
+        (one persistent launch over a work queue, float32 only)."""
+        return poisson_batch_get_mode(self.handle)
+
+    @mode.setter
+    def mode(self, m):
+        poisson_batch_set_mode(self.handle, m)
+
+    def set_queue_radix(self, length, radix_sel):
+        poisson_batch_set_queue_radix(self.handle, length, radix_sel)
+
+    def queue_radix(self, length):
+        return poisson_batch_get_queue_radix(self.handle, length)
+
+    def set_queue_shape(self, tile_elems=2048, item_kb=256):
+        poisson_batch_set_queue_shape(self.handle, tile_elems, item_kb)
+
+    def set_queue_spin(self, spin_limit):
+        poisson_batch_set_queue_spin(self.handle, spin_limit)
+
+    def queue_status(self):
+        """Sticky queue flags since the last call (waits for the device)."""
+        return poisson_batch_queue_status(self.handle)
 
     def tune(self, rho_list, V_list, reps=0, stream=None):
         """Autotune tile schedules and the per-launch budget (V receives

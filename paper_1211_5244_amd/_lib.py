@@ -38,9 +38,16 @@ EXPORTED = (
     "poisson_batch_solve", "poisson_batch_destroy", "poisson_plan_set_schedule",
     "poisson_batch_set_schedule", "poisson_batch_get_schedule", "poisson_plan_get_schedule",
     "poisson_plan_tune", "poisson_set_tune_cache", "poisson_batch_tune", "poisson_batch_set_streams",
-    "poisson_batch_get_streams", "poisson_rel_l2", "poisson_rel_l2_noalloc",
+    "poisson_batch_get_streams", "poisson_batch_set_mode", "poisson_batch_get_mode",
+    "poisson_queue_radices", "poisson_batch_set_queue_radix", "poisson_batch_get_queue_radix",
+    "poisson_batch_set_queue_shape", "poisson_batch_set_queue_spin", "poisson_batch_queue_status",
+    "poisson_queue_simulate", "poisson_rel_l2", "poisson_rel_l2_noalloc",
     "poisson_last_error",
 )
+
+# batch modes (poisson_batch_set_mode)
+POISSON_BATCH_GROUPED, POISSON_BATCH_QUEUE = 0, 1
+QUEUE_ERR_SPIN = 1  # poisson_batch_queue_status: a bounded wait ran out
 
 # schedules per pass (poisson_plan_set_schedule): tile width in bits 0-1,
 # XCD-blocked workgroup order in bit 2, small-grid plane kernel in bit 3 (of
@@ -110,6 +117,16 @@ def load_library(path=None):
         "poisson_batch_kernel_build_isf": (_i, [_vp, _i, _vp]),
         "poisson_batch_set_streams": (_i, [_vp, _i]),
         "poisson_batch_get_streams": (_i, [_vp, ctypes.POINTER(_i)]),
+        "poisson_batch_set_mode": (_i, [_vp, _i]),
+        "poisson_batch_get_mode": (_i, [_vp, ctypes.POINTER(_i)]),
+        "poisson_queue_radices": (_i, [_i, _i, ctypes.POINTER(_i)]),
+        "poisson_batch_set_queue_radix": (_i, [_vp, _i, _i]),
+        "poisson_batch_get_queue_radix": (_i, [_vp, _i, ctypes.POINTER(_i)]),
+        "poisson_batch_set_queue_shape": (_i, [_vp, _i, _i]),
+        "poisson_batch_set_queue_spin": (_i, [_vp, _u]),
+        "poisson_batch_queue_status": (_i, [_vp, ctypes.POINTER(_u)]),
+        "poisson_queue_simulate": (_i, [_i, ctypes.POINTER(_i), _i, _i, _u,
+                                        ctypes.POINTER(ctypes.c_longlong)]),
         "poisson_rel_l2": (_i, [_vp, _vp, _sz, ctypes.POINTER(_d), _vp]),
         "poisson_rel_l2_noalloc": (_i, [_vp, _vp, _sz, _vp, _vp]),
         "poisson_last_error": (ctypes.c_char_p, []),
@@ -352,3 +369,56 @@ def poisson_batch_tune(batch, rho_list, V_list, reps=0, stream=None):
     mb = _d()
     _check(load_library().poisson_batch_tune(batch, r, v, int(reps), ctypes.byref(mb), _stream(stream)))
     return mb.value
+
+
+def poisson_batch_set_mode(batch, mode):
+    _check(load_library().poisson_batch_set_mode(batch, int(mode)))
+
+
+def poisson_batch_get_mode(batch):
+    out = _i()
+    _check(load_library().poisson_batch_get_mode(batch, ctypes.byref(out)))
+    return out.value
+
+
+def poisson_queue_radices(length, radix_sel):
+    """Radices of a queue transform of this length, first stage first."""
+    rad = (_i * 12)()
+    n = load_library().poisson_queue_radices(int(length), int(radix_sel), rad)
+    _check(min(n, 0))
+    return tuple(rad[:n])
+
+
+def poisson_batch_set_queue_radix(batch, length, radix_sel):
+    _check(load_library().poisson_batch_set_queue_radix(batch, int(length), int(radix_sel)))
+
+
+def poisson_batch_get_queue_radix(batch, length):
+    out = _i()
+    _check(load_library().poisson_batch_get_queue_radix(batch, int(length), ctypes.byref(out)))
+    return out.value
+
+
+def poisson_batch_set_queue_shape(batch, tile_elems, item_kb):
+    _check(load_library().poisson_batch_set_queue_shape(batch, int(tile_elems), int(item_kb)))
+
+
+def poisson_batch_set_queue_spin(batch, spin_limit):
+    _check(load_library().poisson_batch_set_queue_spin(batch, int(spin_limit)))
+
+
+def poisson_batch_queue_status(batch):
+    """Waits for the device; returns and clears the sticky queue flags."""
+    out = _u()
+    _check(load_library().poisson_batch_queue_status(batch, ctypes.byref(out)))
+    return out.value
+
+
+def poisson_queue_simulate(seg_items, workers, fault=0, seed=1):
+    """Host simulation of the queue protocol; seg_items[pass][solve] items per
+    segment.  Returns (waits, releases, violations, waits that ran out)."""
+    nsolve = len(seg_items[0])
+    flat = (_i * (5 * nsolve))(*[int(seg_items[k][i]) for k in range(5) for i in range(nsolve)])
+    stats = (ctypes.c_longlong * 4)()
+    _check(load_library().poisson_queue_simulate(nsolve, flat, int(workers), int(fault), int(seed), stats))
+    return tuple(stats)

@@ -29,7 +29,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["plan.cpp", "api.cpp", "kernel_build.hip", "kernel_isf.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernel_build.hip", "kernel_isf.hip", "queue.hip"]
 # the pass kernels are split by FFT length so they compile in parallel
 PASS_LENGTHS = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
 

@@ -11,7 +11,11 @@
 #include <mutex>
 #include <new>
 #include <sstream>
+#include <atomic>
+#include <chrono>
+#include <random>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -20,6 +24,7 @@
 #include "../../include/poisson.h"
 #include "kernels.h"
 #include "plan.h"
+#include "queue.h"
 
 using psn::Geometry;
 
@@ -98,6 +103,21 @@ struct poisson_batch_s {
   std::vector<hipStream_t> side;            // the batch's own streams (lanes - 1 used)
   std::vector<hipEvent_t> events;           // fork event, then one join event per side stream
   int device = 0;
+  // the persistent schedule (float32): one launch over a pass-ordered queue
+  int mode = POISSON_BATCH_GROUPED;
+  std::map<int, int> q_radix;               // radix choice per line length (absent: 0)
+  int q_tile = psn::kQMaxTile;              // complex elements per tile
+  int q_item_kb = 256;                      // target bytes (in + out) per work item
+  unsigned q_spin = 1u << 20;               // bound of every wait (about a second of polls)
+  bool q_dirty = true;                      // descriptors to rebuild before the next launch
+  void *q_desc = nullptr;                   // geometries, solve table, segments
+  size_t q_desc_bytes = 0;
+  unsigned *q_state = nullptr;              // queue counters (zero between launches)
+  void *q_ws = nullptr;                     // every solve's intermediates
+  size_t q_ws_bytes = 0;
+  std::vector<psn::QSolve> q_solves;        // host copy of the device solve table
+  psn::QParams q_params{};
+  int q_grid = 0;
 };
 
 namespace {
@@ -629,6 +649,167 @@ int enqueue_passes(poisson_plan_t P, int count, const float *const *rho, float *
   return POISSON_OK;
 }
 
+// ----------------------------------------------- persistent batch schedule
+// Queue descriptor of pass k of plan P (radix choice and tile shape from B).
+int queue_pass(poisson_batch_t B, poisson_plan_t P, int k, psn::QPass &Q) {
+  const Geometry &g = P->g;
+  const psn::Pass &pp = g.pass[k];
+  const int axis[5] = {g.order[0], g.order[1], g.order[2], g.order[1], g.order[0]};
+  Q = psn::QPass{};
+  Q.tw = P->tw[axis[k]];
+  for (int i = 0; i < 3; ++i) {
+    Q.in_s[i] = pp.in_s[i];
+    Q.out_s[i] = pp.out_s[i];
+  }
+  Q.kind = pp.kind;
+  Q.L = pp.L;
+  Q.n_in = pp.n_in;
+  Q.n_out = pp.n_out;
+  Q.pad = pp.pad ? 1 : 0;
+  Q.ext_tile = pp.ext_tile;
+  Q.ext_batch = pp.ext_batch;
+  Q.C = std::max(1, B->q_tile / pp.L);
+  const bool real = pp.kind == psn::KIND_R2C || pp.kind == psn::KIND_C2R;
+  Q.W = real ? 2 * Q.C : Q.C;
+  Q.tiles_a = (Q.ext_tile + Q.W - 1) / Q.W;
+  Q.ntiles = Q.tiles_a * Q.ext_batch;
+  const double tile_bytes = double(Q.C) * pp.L * 16.0;  // complex lines in and out
+  Q.G = std::max(1, int(B->q_item_kb * 1024.0 / tile_bytes));
+  auto it = B->q_radix.find(pp.L);
+  Q.nrad = psn::q_radices(pp.L, it == B->q_radix.end() ? 0 : it->second, Q.rad);
+  if (Q.nrad == 0) return fail(POISSON_E_STATE, "internal error: no radix decomposition");
+  return POISSON_OK;
+}
+
+// (Re)builds the queue's descriptors, counters and workspace.  Waits for the
+// device: descriptors in use by an earlier launch are replaced.
+int queue_build(poisson_batch_t B) {
+  const int ns = int(B->which.size()), nplan = int(B->plans.size());
+  std::vector<psn::QGeom> geoms(nplan);
+  for (int u = 0; u < nplan; ++u) {
+    poisson_plan_t P = B->plans[u];
+    for (int k = 0; k < 5; ++k) {
+      int rc = queue_pass(B, P, k, geoms[u].pass[k]);
+      if (rc) return rc;
+    }
+    geoms[u].kf = P->kf32;
+    geoms[u].S_q = P->g.S[P->g.order[1]];
+    geoms[u].kq_half = geoms[u].S_q / 2 + 1;
+  }
+  const int nseg = psn::kQLevels * ns;
+  std::vector<psn::QSeg> segs(nseg);
+  psn::QParams &a = B->q_params;
+  a = psn::QParams{};
+  long long first = 0;
+  for (int k = 0; k < psn::kQLevels; ++k)
+    for (int i = 0; i < ns; ++i) {
+      const psn::QPass &Q = geoms[B->which[i]].pass[k];
+      const int cnt = (Q.ntiles + Q.G - 1) / Q.G;
+      segs[k * ns + i] = {int(first), cnt, i, k};
+      first += cnt;
+      a.level_items[k] += cnt;
+    }
+  if (first >= (1LL << 30)) return fail(POISSON_E_UNSUPPORTED, "batch too large for the queue schedule");
+  // every solve's intermediates, 256-byte aligned
+  std::vector<size_t> off(ns);
+  size_t ws = 0;
+  for (int i = 0; i < ns; ++i) {
+    off[i] = ws;
+    ws += B->plans[B->which[i]]->g.ws_bytes;
+  }
+  auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t geo_b = align(sizeof(psn::QGeom) * nplan), sol_b = align(sizeof(psn::QSolve) * ns),
+               seg_b = align(sizeof(psn::QSeg) * nseg);
+  PSN_TRY_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  auto grow = [&](void **ptr, size_t &have, size_t need, const char *what) -> int {
+    if (have >= need && *ptr) return POISSON_OK;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    have = 0;
+    hipError_t e = hipMalloc(ptr, need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *ptr = nullptr;
+      hip_fail(e, what);
+      return e == hipErrorOutOfMemory ? POISSON_E_NOMEM : POISSON_E_HIP;
+    }
+    have = need;
+    return POISSON_OK;
+  };
+  int rc = grow(&B->q_desc, B->q_desc_bytes, geo_b + sol_b + seg_b, "hipMalloc(queue descriptors)");
+  if (rc) return rc;
+  rc = grow(&B->q_ws, B->q_ws_bytes, std::max<size_t>(ws, 256), "hipMalloc(queue workspace)");
+  if (rc) return rc;
+  if (!B->q_state) {
+    void *st = nullptr;
+    size_t have = 0;
+    rc = grow(&st, have, sizeof(unsigned) * (psn::kQStateHeader + nseg), "hipMalloc(queue counters)");
+    if (rc) return rc;
+    B->q_state = static_cast<unsigned *>(st);
+    PSN_TRY_HIP(hipMemset(B->q_state, 0, have), "hipMemset(queue counters)");
+  }
+  char *d = static_cast<char *>(B->q_desc);
+  PSN_TRY_HIP(hipMemcpy(d, geoms.data(), sizeof(psn::QGeom) * nplan, hipMemcpyHostToDevice),
+              "hipMemcpy(queue geometries)");
+  PSN_TRY_HIP(hipMemcpy(d + geo_b + sol_b, segs.data(), sizeof(psn::QSeg) * nseg, hipMemcpyHostToDevice),
+              "hipMemcpy(queue segments)");
+  B->q_solves.assign(ns, psn::QSolve{});
+  char *wsb = static_cast<char *>(B->q_ws);
+  for (int i = 0; i < ns; ++i) {
+    const Geometry &g = B->plans[B->which[i]]->g;
+    B->q_solves[i].geom = B->which[i];
+    B->q_solves[i].a1 = reinterpret_cast<float2 *>(wsb + off[i]);
+    B->q_solves[i].a2 = reinterpret_cast<float2 *>(wsb + off[i] + g.a1_bytes);
+  }
+  // the solve table goes up with the first solve's arrays
+  a.geoms = reinterpret_cast<const psn::QGeom *>(d);
+  a.solves = reinterpret_cast<const psn::QSolve *>(d + geo_b);
+  a.segs = reinterpret_cast<const psn::QSeg *>(d + geo_b + sol_b);
+  a.state = B->q_state;
+  a.nsolve = ns;
+  a.nseg = nseg;
+  a.nitems = int(first);
+  int per_cu = 0, cus = 0;
+  PSN_TRY_HIP(psn::queue_occupancy(&per_cu), "queue occupancy");
+  PSN_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device),
+              "hipDeviceGetAttribute");
+  B->q_grid = std::max(1, std::min(a.nitems, std::max(1, per_cu) * cus));
+  B->q_dirty = false;
+  return POISSON_OK;
+}
+
+int queue_solve(poisson_batch_t B, const float *const *rho, float *const *V, hipStream_t s) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  PSN_TRY_HIP(hipStreamIsCapturing(s, &cap), "hipStreamIsCapturing");
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (B->q_dirty) {
+    if (capturing)
+      return fail(POISSON_E_STATE, "queue schedule changed: run one solve outside graph capture first");
+    int rc = queue_build(B);
+    if (rc) return rc;
+  }
+  const int ns = int(B->which.size());
+  bool changed = false;
+  for (int i = 0; i < ns && !changed; ++i)
+    changed = B->q_solves[i].rho != rho[i] || B->q_solves[i].V != V[i];
+  if (changed) {
+    if (capturing)
+      return fail(POISSON_E_STATE, "new arrays: run one solve with them outside graph capture first");
+    PSN_TRY_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");  // the table may be in use
+    for (int i = 0; i < ns; ++i) {
+      B->q_solves[i].rho = rho[i];
+      B->q_solves[i].V = V[i];
+    }
+    PSN_TRY_HIP(hipMemcpy(const_cast<psn::QSolve *>(B->q_params.solves), B->q_solves.data(),
+                          sizeof(psn::QSolve) * ns, hipMemcpyHostToDevice),
+                "hipMemcpy(queue solve table)");
+  }
+  B->q_params.spin_limit = B->q_spin;
+  hipError_t e = psn::launch_queue(B->q_params, B->q_grid, s);
+  if (e != hipSuccess) return hip_fail(e, "queue launch");
+  return POISSON_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -819,6 +1000,7 @@ int poisson_batch_solve(poisson_batch_t B, const float *const *rho, float *const
   DeviceScope ds(B->device);
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the batch's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (B->mode == POISSON_BATCH_QUEUE) return queue_solve(B, rho, V, s);
   // the chunks: up to chunk[u] solves of plan u per launch
   struct Chunk {
     int u, start, cnt;
@@ -900,11 +1082,199 @@ int poisson_batch_destroy(poisson_batch_t B) {
     DeviceScope ds(B->device);
     (void)hipDeviceSynchronize();
     if (B->ws) (void)hipFree(B->ws);
+    if (B->q_desc) (void)hipFree(B->q_desc);
+    if (B->q_state) (void)hipFree(B->q_state);
+    if (B->q_ws) (void)hipFree(B->q_ws);
     for (hipStream_t st : B->side) (void)hipStreamDestroy(st);
     for (hipEvent_t ev : B->events) (void)hipEventDestroy(ev);
   }
   for (auto *P : B->plans) poisson_plan_destroy(P);
   delete B;
+  return POISSON_OK;
+}
+
+int poisson_batch_set_mode(poisson_batch_t B, int mode) {
+  if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  if (mode != POISSON_BATCH_GROUPED && mode != POISSON_BATCH_QUEUE)
+    return fail(POISSON_E_ARG, "mode must be POISSON_BATCH_GROUPED or POISSON_BATCH_QUEUE");
+  if (mode == POISSON_BATCH_QUEUE && B->plans[0]->precision != POISSON_FP32)
+    return fail(POISSON_E_UNSUPPORTED, "the queue schedule runs float32 batches only");
+  B->mode = mode;
+  return POISSON_OK;
+}
+
+int poisson_batch_get_mode(poisson_batch_t B, int *mode) {
+  if (!B || !mode) return fail(POISSON_E_ARG, "NULL argument");
+  *mode = B->mode;
+  return POISSON_OK;
+}
+
+int poisson_queue_radices(int length, int radix_sel, int radices[12]) {
+  if (!radices) return fail(POISSON_E_ARG, "radices is NULL");
+  if (!psn::supported_length(length)) return fail(POISSON_E_UNSUPPORTED, "length not supported");
+  const int n = psn::q_radices(length, radix_sel, radices);
+  if (n == 0) return fail(POISSON_E_ARG, "radix choice must be 0, 1 or 2");
+  return n;
+}
+
+int poisson_batch_set_queue_radix(poisson_batch_t B, int length, int radix_sel) {
+  if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  int rad[psn::kQMaxRadices];
+  if (!psn::supported_length(length)) return fail(POISSON_E_UNSUPPORTED, "length not supported");
+  if (psn::q_radices(length, radix_sel, rad) == 0) return fail(POISSON_E_ARG, "radix choice must be 0, 1 or 2");
+  B->q_radix[length] = radix_sel;
+  B->q_dirty = true;
+  return POISSON_OK;
+}
+
+int poisson_batch_get_queue_radix(poisson_batch_t B, int length, int *radix_sel) {
+  if (!B || !radix_sel) return fail(POISSON_E_ARG, "NULL argument");
+  auto it = B->q_radix.find(length);
+  *radix_sel = it == B->q_radix.end() ? 0 : it->second;
+  return POISSON_OK;
+}
+
+int poisson_batch_set_queue_shape(poisson_batch_t B, int tile_elems, int item_kb) {
+  if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  if (tile_elems < 64 || tile_elems > psn::kQMaxTile || (tile_elems & (tile_elems - 1)))
+    return fail(POISSON_E_ARG, "tile_elems must be a power of two, 64 to 2048");
+  if (item_kb < 1 || item_kb > (1 << 20)) return fail(POISSON_E_ARG, "item_kb must be 1 to 2^20");
+  B->q_tile = tile_elems;
+  B->q_item_kb = item_kb;
+  B->q_dirty = true;
+  return POISSON_OK;
+}
+
+int poisson_batch_set_queue_spin(poisson_batch_t B, unsigned spin_limit) {
+  if (!B) return fail(POISSON_E_ARG, "batch is NULL");
+  if (spin_limit == 0) return fail(POISSON_E_ARG, "spin_limit must be positive");
+  B->q_spin = spin_limit;
+  return POISSON_OK;
+}
+
+int poisson_batch_queue_status(poisson_batch_t B, unsigned *flags) {
+  if (!B || !flags) return fail(POISSON_E_ARG, "NULL argument");
+  *flags = 0;
+  if (!B->q_state) return POISSON_OK;
+  DeviceScope ds(B->device);
+  if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the batch's device");
+  PSN_TRY_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  PSN_TRY_HIP(hipMemcpy(flags, B->q_state + psn::kQError, sizeof(unsigned), hipMemcpyDeviceToHost),
+              "hipMemcpy(queue flags)");
+  PSN_TRY_HIP(hipMemset(B->q_state + psn::kQError, 0, sizeof(unsigned)), "hipMemset(queue flags)");
+  return POISSON_OK;
+}
+
+// Host simulation of the queue protocol (queue.h): `workers` threads play
+// workgroups over segments of seg_items[pass * nsolve + solve] items with the
+// same ordering, flush and wait rules as the device kernel, and check that
+// every item of a dependency segment had finished its work when a dependent
+// item passed its wait, that every item ran once and that the counters end at
+// zero.  fault (for tests of the checks): 1 skips the flush before a higher
+// level, 2 marks an item complete before its work.
+int poisson_queue_simulate(int nsolve, const int *seg_items, int workers, int fault, unsigned seed,
+                           long long stats[4]) {
+  if (nsolve < 1 || !seg_items || workers < 1 || workers > 256 || fault < 0 || fault > 2)
+    return fail(POISSON_E_ARG, "bad simulation arguments");
+  const int nseg = psn::kQLevels * nsolve;
+  std::vector<psn::QSeg> segs(nseg);
+  long long level_items[psn::kQLevels] = {0, 0, 0, 0, 0};
+  long long first = 0;
+  for (int k = 0; k < psn::kQLevels; ++k)
+    for (int i = 0; i < nsolve; ++i) {
+      const int cnt = seg_items[k * nsolve + i];
+      if (cnt < 1) return fail(POISSON_E_ARG, "every segment needs at least one item");
+      segs[k * nsolve + i] = {int(first), cnt, i, k};
+      first += cnt;
+      level_items[k] += cnt;
+    }
+  if (first > (1 << 24)) return fail(POISSON_E_ARG, "too many items to simulate");
+  const unsigned nitems = unsigned(first);
+  std::atomic<unsigned> head{0}, exitc{0}, err{0};
+  std::vector<std::atomic<unsigned>> lvl(psn::kQLevels), segc(nseg), work(nseg), taken(nitems);
+  for (auto &x : lvl) x = 0;
+  for (auto &x : segc) x = 0;
+  for (auto &x : work) x = 0;
+  for (auto &x : taken) x = 0;
+  std::atomic<long long> waits{0}, flushes{0}, violations{0}, timeouts{0};
+  auto worker = [&](int id) {
+    std::mt19937 rng(seed * 7919u + unsigned(id));
+    int npend = 0, pend_level = 0, acq_level = -1;
+    int pend[psn::kQPending];
+    auto flush = [&] {
+      for (int j = 0; j < npend; ++j) segc[pend[j]].fetch_add(1);
+      lvl[pend_level].fetch_add(unsigned(npend));
+      flushes.fetch_add(1);
+      npend = 0;
+    };
+    for (;;) {
+      const unsigned item = head.fetch_add(1);
+      if (item >= nitems) break;
+      taken[item].fetch_add(1);
+      const int si = psn::q_find_seg(segs.data(), nseg, int(item));
+      const int k = segs[si].pass;
+      // fault 1 releases lower-level items only after the wait below
+      if (psn::q_must_flush(npend, pend_level, k) && (fault != 1 || pend_level == k)) flush();
+      if (psn::q_must_wait(k, acq_level)) {
+        const int dep = psn::q_dep_seg(si, nsolve);
+        bool full = false;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (;;) {
+          if (lvl[k - 1].load() >= level_items[k - 1]) { full = true; break; }
+          if (segc[dep].load() >= unsigned(segs[dep].count)) break;
+          if (err.load() || std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(500)) {
+            err.fetch_or(1u);
+            timeouts.fetch_add(1);
+            break;
+          }
+          std::this_thread::yield();
+        }
+        waits.fetch_add(1);
+        if (full) acq_level = k - 1;
+      }
+      if (k > 0 && work[si - nsolve].load() != unsigned(segs[si - nsolve].count)) violations.fetch_add(1);
+      if (fault == 2) {
+        segc[si].fetch_add(1);
+        lvl[k].fetch_add(1);
+      }
+      if (fault == 2) std::this_thread::sleep_for(std::chrono::milliseconds(5));
+      else if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 50));
+      work[si].fetch_add(1);
+      if (fault != 2) {
+        if (npend > 0 && pend_level != k) flush();  // (only under fault 1: a list holds one level)
+        pend[npend++] = si;
+        pend_level = k;
+      }
+    }
+    if (npend > 0) flush();
+    if (exitc.fetch_add(1) == unsigned(workers - 1)) {
+      for (auto &x : segc) x = 0;
+      for (auto &x : lvl) x = 0;
+      head = 0;
+      exitc = 0;
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int w = 0; w < workers; ++w) pool.emplace_back(worker, w);
+  } catch (...) {
+    for (auto &t : pool) t.join();
+    return fail(POISSON_E_STATE, "cannot start simulation threads");
+  }
+  for (auto &t : pool) t.join();
+  if (stats) {
+    stats[0] = waits.load();
+    stats[1] = flushes.load();
+    stats[2] = violations.load();
+    stats[3] = timeouts.load();
+  }
+  for (unsigned i = 0; i < nitems; ++i)
+    if (taken[i].load() != 1u) return fail(POISSON_E_STATE, "simulation: an item ran " + std::to_string(taken[i].load()) + " times");
+  if (violations.load()) return fail(POISSON_E_STATE, "simulation: an item started before its dependency finished");
+  if (err.load()) return fail(POISSON_E_STATE, "simulation: a wait ran out");
+  for (auto &x : segc)
+    if (x.load()) return fail(POISSON_E_STATE, "simulation: counters not reset");
+  if (head.load() || exitc.load()) return fail(POISSON_E_STATE, "simulation: queue head not reset");
   return POISSON_OK;
 }
 
@@ -1132,6 +1502,7 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
   if (!ds.ok) return fail(POISSON_E_HIP, "cannot select the batch's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (reps <= 0) reps = 5;
+  B->mode = POISSON_BATCH_GROUPED;  // steps 1-3 tune the grouped launches
   // 1. tile schedules of every plan, timed on its first chunk
   std::vector<const float *> r(psn::kMaxBatch);
   std::vector<float *> v(psn::kMaxBatch);
@@ -1198,6 +1569,77 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
       }
     }
     B->lanes = best_lanes;
+  }
+  // 4. float32: the persistent schedule, radix choice per line length
+  // (coordinate descent over the lengths), then the item size; it becomes
+  // the batch's schedule only if it beats the grouped launches
+  if (B->plans[0]->precision == POISSON_FP32) {
+    double grouped = INFINITY;
+    int rc = time_enqueue([&] { return poisson_batch_solve(B, rho, V, stream); }, s, reps, &grouped);
+    if (rc) return rc;
+    B->mode = POISSON_BATCH_QUEUE;
+    auto timed = [&](double *t) {
+      return time_enqueue([&] { return poisson_batch_solve(B, rho, V, stream); }, s, reps, t);
+    };
+    double qbest = INFINITY;
+    rc = timed(&qbest);
+    if (rc) {
+      B->mode = POISSON_BATCH_GROUPED;
+      return rc;
+    }
+    std::vector<int> lengths;
+    for (auto *P : B->plans)
+      for (int k = 0; k < 5; ++k)
+        if (std::find(lengths.begin(), lengths.end(), P->g.pass[k].L) == lengths.end())
+          lengths.push_back(P->g.pass[k].L);
+    std::sort(lengths.begin(), lengths.end());
+    for (int L : lengths) {
+      auto it = B->q_radix.find(L);
+      const int cur = it == B->q_radix.end() ? 0 : it->second;
+      int keep = cur;
+      int rad[psn::kQMaxRadices];
+      const int n0 = psn::q_radices(L, cur, rad);
+      for (int sel = 0; sel < psn::kQRadixChoices; ++sel) {
+        if (sel == cur) continue;
+        int other[psn::kQMaxRadices];
+        const int n1 = psn::q_radices(L, sel, other);
+        if (n1 == n0 && std::equal(rad, rad + n0, other)) continue;  // the same stages
+        B->q_radix[L] = sel;
+        B->q_dirty = true;
+        double t = 0;
+        rc = timed(&t);
+        if (rc) {
+          B->mode = POISSON_BATCH_GROUPED;
+          return rc;
+        }
+        if (t < 0.99 * qbest) {
+          qbest = t;
+          keep = sel;
+        }
+      }
+      B->q_radix[L] = keep;
+      B->q_dirty = true;
+    }
+    const int kb0 = B->q_item_kb;
+    int best_kb = kb0;
+    for (int kb : {64, 1024}) {
+      if (kb == kb0) continue;
+      B->q_item_kb = kb;
+      B->q_dirty = true;
+      double t = 0;
+      rc = timed(&t);
+      if (rc) {
+        B->mode = POISSON_BATCH_GROUPED;
+        return rc;
+      }
+      if (t < 0.99 * qbest) {
+        qbest = t;
+        best_kb = kb;
+      }
+    }
+    B->q_item_kb = best_kb;
+    B->q_dirty = true;
+    B->mode = qbest < grouped ? POISSON_BATCH_QUEUE : POISSON_BATCH_GROUPED;
   }
   return POISSON_OK;
 }

@@ -23,18 +23,6 @@ struct PassIO {
 // One pass on `stream` for io.count solves: reads io.in[j], writes io.out[j]
 // (complex intermediates are float2, density and potential float).  `tw` is
 // the table exp(-2 pi i n / L), n = 0..L-1, of the pass's length; `kf` the
-// float64 K^F octant of the free-boundary Green's function on Deslauriers-
-// Dubuc interpolating scaling functions of even order 8..32 (fully free
-// geometries), written to `kf64`.  `scratch` (device, at least
-// isf_table_bytes(g)) holds the quadrature nodes and per-node DCT tables; the
-// node records are copied there with a blocking copy, the kernels are
-// enqueued on `stream`.  hipErrorInvalidValue for an order out of range or
-// too little scratch.
-size_t isf_table_bytes(const Geometry &g);
-hipError_t launch_isf_build(const Geometry &g, double h, int order, double *kf64, void *scratch,
-                            size_t scratch_bytes, const double *const cos_tabs[3],
-                            hipStream_t stream);
-
 // float32 K^F in pass order (conv pass only).  `mode` selects float32
 // radix stages (0) or split-precision matrix-core radix-8 stages (1: fp16
 // hi+lo, 2: bf16 three-way).  Returns a hipError_t.
@@ -100,5 +88,12 @@ hipError_t launch_rel_l2_partials(const float *v, const double *ref, size_t coun
 // share the scratch and race.
 hipError_t launch_rel_l2_noalloc(const float *v, const double *ref, size_t count, double *out,
                                  hipStream_t stream);
+
+// The persistent batched solve (queue.h): one launch of `grid` workgroups
+// on `stream`; queue_occupancy gives the workgroups per compute unit that
+// fit at once.
+struct QParams;
+hipError_t launch_queue(const QParams &a, int grid, hipStream_t stream);
+hipError_t queue_occupancy(int *blocks_per_cu);
 
 }  // namespace psn

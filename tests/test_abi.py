@@ -196,6 +196,15 @@ def test_null_handles_of_the_later_entry_points():
     assert lib.poisson_batch_get_streams(None, None) == E
     assert lib.poisson_rel_l2_noalloc(None, None, 0, None, None) == E
     assert lib.poisson_rel_l2_noalloc(None, None, 16, None, None) == E
+    assert lib.poisson_batch_set_mode(None, 1) == E
+    assert lib.poisson_batch_get_mode(None, None) == E
+    assert lib.poisson_batch_set_queue_radix(None, 64, 0) == E
+    assert lib.poisson_batch_get_queue_radix(None, 64, None) == E
+    assert lib.poisson_batch_set_queue_shape(None, 2048, 256) == E
+    assert lib.poisson_batch_set_queue_spin(None, 1) == E
+    assert lib.poisson_batch_queue_status(None, None) == E
+    assert lib.poisson_queue_radices(64, 0, None) == E
+    assert lib.poisson_queue_simulate(0, None, 1, 0, 1, None) == E
     out = ctypes.c_void_p()
     bad = (ctypes.c_int * 3)(0, 0, 1)
     assert lib.poisson_plan_ordered(ctypes.byref(out), 8, 8, 8, 7, 0.3, 0, bad) == E
