@@ -193,8 +193,27 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     t_one_stream = timed(batched)
     same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
     B.streams = default_streams
+    # float32: the persistent schedule, one launch over a pass-ordered device
+    # queue (its own line transforms: equal to the loop to float32 rounding)
+    queue = {}
+    if precision == 0:
+        B.mode = P.POISSON_BATCH_QUEUE
+        t_queue = timed(batched)
+        queue_diff = max_rel_diff()
+        g3 = torch.cuda.CUDAGraph()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g3):
+                P.poisson_batch_solve(B.handle, rhos, Vs, torch.cuda.current_stream(dev))
+        torch.cuda.synchronize()
+        t_queue_graph = timed(g3.replay)
+        queue_diff = max(queue_diff, max_rel_diff())
+        queue_flags = B.queue_status()
+        B.mode = P.POISSON_BATCH_GROUPED
+        queue = {"queue": t_queue, "queue_graph": t_queue_graph}
     # the autotuner: tile schedules per distinct plan, the per-launch budget,
-    # then the number of concurrent streams
+    # the number of concurrent streams, then (float32) the queue's radix
+    # choices and item size, keeping whichever schedule is faster
     chunk_mb = B.tune(rhos, Vs)
     t_tuned = timed(batched)
     # tuned schedules may use the small-grid plane kernel, equal to float32 rounding only
@@ -214,11 +233,17 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
            "tuned_identical_to_loop": tuned_diff == 0.0,
            "untuned_identical_to_loop": bool(same),
            "tuned_max_rel_l2_vs_loop": tuned_diff, "tuned_chunk_mb": chunk_mb,
-           "default_streams": default_streams, "tuned_streams": B.streams}
+           "default_streams": default_streams, "tuned_streams": B.streams,
+           "tuned_mode": "queue" if B.mode == P.POISSON_BATCH_QUEUE else "grouped"}
+    if queue:
+        out["queue_max_rel_l2_vs_loop"] = queue_diff
+        out["queue_flags"] = queue_flags
     for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph),
                     ("batched_one_stream", t_one_stream),
-                    ("batched_tuned", t_tuned), ("batched_tuned_graph", t_tuned_graph)):
-        a = alg_tuned if "tuned" in name else alg
+                    ("batched_tuned", t_tuned), ("batched_tuned_graph", t_tuned_graph),
+                    *queue.items()):
+        # the queue runs the five-pass geometry (no plane kernel)
+        a = alg_tuned if "tuned" in name and B.mode == P.POISSON_BATCH_GROUPED else alg
         out[name] = {"ms": t, "solves_per_s": len(items) / (t * 1e-3),
                      "alg_gbs": a / (t * 1e-3) / 1e9}
     return out

@@ -321,7 +321,8 @@ int poisson_set_tune_cache(const char *path);
  * 32..512 MiB and keeps the fastest (chunk_mb, may be NULL, receives it),
  * then the number of concurrent streams (1..4, poisson_batch_set_streams)
  * at that budget.  A float32 batch then times the persistent schedule
- * (radix choice per line length, then items of 64, 256 or 1024 KiB) and
+ * (radix choice per line length, then tiles of 1024 or 2048 elements with
+ * items of 128, 512 or 2048 KiB) and
  * keeps it as the batch's mode only if it beats the grouped launches
  * (poisson_batch_get_mode tells which).  The arrays are those of
  * poisson_batch_solve; V receives
@@ -384,9 +385,9 @@ int poisson_queue_radices(int length, int radix_sel, int radices[12]);
 int poisson_batch_set_queue_radix(poisson_batch_t batch, int length, int radix_sel);
 int poisson_batch_get_queue_radix(poisson_batch_t batch, int length, int *radix_sel);
 /* Tile of the queue transforms: tile_elems complex elements (power of two,
- * 64..2048; default 2048) hold tile_elems / L lines of length L (at least
- * one); an item is as many tiles as carry about item_kb KiB in and out
- * (default 256). */
+ * 64..2048; default 2048) hold the largest power of two of lines of length
+ * L that fits (at least one); an item is as many tiles as carry about
+ * item_kb KiB in and out (default 512). */
 int poisson_batch_set_queue_shape(poisson_batch_t batch, int tile_elems, int item_kb);
 /* Spin limit of every queue wait (default 2^20 polls, on the order of a
  * second; > 0). */

@@ -232,7 +232,7 @@ class Batch:
     def queue_radix(self, length):
         return poisson_batch_get_queue_radix(self.handle, length)
 
-    def set_queue_shape(self, tile_elems=2048, item_kb=256):
+    def set_queue_shape(self, tile_elems=2048, item_kb=512):
         poisson_batch_set_queue_shape(self.handle, tile_elems, item_kb)
 
     def set_queue_spin(self, spin_limit):

@@ -107,7 +107,7 @@ struct poisson_batch_s {
   int mode = POISSON_BATCH_GROUPED;
   std::map<int, int> q_radix;               // radix choice per line length (absent: 0)
   int q_tile = psn::kQMaxTile;              // complex elements per tile
-  int q_item_kb = 256;                      // target bytes (in + out) per work item
+  int q_item_kb = 512;                      // target bytes (in + out) per work item
   unsigned q_spin = 1u << 20;               // bound of every wait (about a second of polls)
   bool q_dirty = true;                      // descriptors to rebuild before the next launch
   void *q_desc = nullptr;                   // geometries, solve table, segments
@@ -668,7 +668,10 @@ int queue_pass(poisson_batch_t B, poisson_plan_t P, int k, psn::QPass &Q) {
   Q.pad = pp.pad ? 1 : 0;
   Q.ext_tile = pp.ext_tile;
   Q.ext_batch = pp.ext_batch;
-  Q.C = std::max(1, B->q_tile / pp.L);
+  // C: the largest power of two with C L <= tile (at least 1)
+  Q.c_log2 = 0;
+  while ((2 << Q.c_log2) * pp.L <= B->q_tile) ++Q.c_log2;
+  Q.C = 1 << Q.c_log2;
   const bool real = pp.kind == psn::KIND_R2C || pp.kind == psn::KIND_C2R;
   Q.W = real ? 2 * Q.C : Q.C;
   Q.tiles_a = (Q.ext_tile + Q.W - 1) / Q.W;
@@ -678,6 +681,21 @@ int queue_pass(poisson_batch_t B, poisson_plan_t P, int k, psn::QPass &Q) {
   auto it = B->q_radix.find(pp.L);
   Q.nrad = psn::q_radices(pp.L, it == B->q_radix.end() ? 0 : it->second, Q.rad);
   if (Q.nrad == 0) return fail(POISSON_E_STATE, "internal error: no radix decomposition");
+  int ns = 1;
+  for (int st = 0; st < Q.nrad; ++st) {
+    int m = ns, sh = 0;
+    Q.ns_three[st] = m % 3 == 0 ? 1 : 0;
+    if (Q.ns_three[st]) m /= 3;
+    while (m > 1) { m >>= 1; ++sh; }
+    Q.ns_shift[st] = sh;
+    Q.tw_step[st] = pp.L / (ns * Q.rad[st]);
+    ns *= Q.rad[st];
+  }
+  // element offsets are 32-bit on the device
+  const long long big = (1LL << 31) - 1;
+  for (int i = 0; i < 3; ++i)
+    if (std::llabs(Q.in_s[i]) > big || std::llabs(Q.out_s[i]) > big)
+      return fail(POISSON_E_UNSUPPORTED, "array too large for the queue schedule");
   return POISSON_OK;
 }
 
@@ -1571,8 +1589,8 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
     B->lanes = best_lanes;
   }
   // 4. float32: the persistent schedule, radix choice per line length
-  // (coordinate descent over the lengths), then the item size; it becomes
-  // the batch's schedule only if it beats the grouped launches
+  // (coordinate descent over the lengths), then the tile and item size; it
+  // becomes the batch's schedule only if it beats the grouped launches
   if (B->plans[0]->precision == POISSON_FP32) {
     double grouped = INFINITY;
     int rc = time_enqueue([&] { return poisson_batch_solve(B, rho, V, stream); }, s, reps, &grouped);
@@ -1620,24 +1638,28 @@ int poisson_batch_tune(poisson_batch_t B, const float *const *rho, float *const 
       B->q_radix[L] = keep;
       B->q_dirty = true;
     }
-    const int kb0 = B->q_item_kb;
-    int best_kb = kb0;
-    for (int kb : {64, 1024}) {
-      if (kb == kb0) continue;
-      B->q_item_kb = kb;
-      B->q_dirty = true;
-      double t = 0;
-      rc = timed(&t);
-      if (rc) {
-        B->mode = POISSON_BATCH_GROUPED;
-        return rc;
+    const int kb0 = B->q_item_kb, tile0 = B->q_tile;
+    int best_kb = kb0, best_tile = tile0;
+    for (int tile : {1024, 2048})
+      for (int kb : {128, 512, 2048}) {
+        if (kb == kb0 && tile == tile0) continue;
+        B->q_item_kb = kb;
+        B->q_tile = tile;
+        B->q_dirty = true;
+        double t = 0;
+        rc = timed(&t);
+        if (rc) {
+          B->mode = POISSON_BATCH_GROUPED;
+          return rc;
+        }
+        if (t < 0.99 * qbest) {
+          qbest = t;
+          best_kb = kb;
+          best_tile = tile;
+        }
       }
-      if (t < 0.99 * qbest) {
-        qbest = t;
-        best_kb = kb;
-      }
-    }
     B->q_item_kb = best_kb;
+    B->q_tile = best_tile;
     B->q_dirty = true;
     B->mode = qbest < grouped ? POISSON_BATCH_QUEUE : POISSON_BATCH_GROUPED;
   }

@@ -67,8 +67,12 @@ struct QPass {
   int tiles_a;                   // tiles along the tile axis
   int ntiles;                    // tiles_a * ext_batch
   int G;                         // tiles per item
+  int c_log2;                    // log2 C (C is a power of two)
   int nrad;
   int rad[kQMaxRadices];         // radices of the line transform, first stage first
+  // per stage: span NS = product of the earlier radices as NS = 2^ns_shift
+  // * (ns_three ? 3 : 1), and the twiddle step L / (NS R)
+  int ns_shift[kQMaxRadices], ns_three[kQMaxRadices], tw_step[kQMaxRadices];
 };
 
 struct QGeom {

@@ -23,100 +23,143 @@ namespace {
 // LDS slot of complex element i of a tile: one pad slot per 32.
 __device__ __forceinline__ int qx(int i) { return i + (i >> 5); }
 constexpr int kQSlots = kQMaxTile + kQMaxTile / 32;
+constexpr int kQTwSlots = 1024;  // the longest line's twiddle table
 
 __device__ __forceinline__ float2 fzero() { return make_float2(0.f, 0.f); }
 
-// One radix-R butterfly of a Stockham stage with span NS over the lines of
-// a tile: reads src[c][j + m L/R], writes dst[c][(j / NS) NS R + j % NS + m NS].
-template <int R, bool INV, bool ZHI>
-__device__ __forceinline__ void q_bfly(const float2 *src, float2 *dst, int c, int j, int L, int NS,
-                                       const float2 *__restrict__ tw) {
-  const int Lr = L / R, k = j % NS, base = c * L;
-  float2 x[R];
-#pragma unroll
-  for (int m = 0; m < R; ++m) x[m] = (ZHI && m >= R / 2) ? fzero() : src[qx(base + j + m * Lr)];
-  if (NS > 1) {
-    const int step = L / (NS * R);
-#pragma unroll
-    for (int m = 1; m < R; ++m) x[m] = cmul_tw<INV>(x[m], tw[k * m * step]);
-  }
-  dft<R, INV, ZHI>(x);
-  const int o = base + (j / NS) * NS * R + k;
-#pragma unroll
-  for (int m = 0; m < R; ++m) dst[qx(o + m * NS)] = x[m];
+// x / d and x % d for d = 2^shift (three = 0) or 3 * 2^shift (three = 1):
+// 0xAAAAAAAB / 2^33 rounds up 1/3 closely enough to be exact for every
+// 32-bit x.
+__device__ __forceinline__ int qdiv(int x, int shift, int three) {
+  const unsigned y = unsigned(x) >> shift;
+  return int(three ? __umulhi(y, 0xAAAAAAABu) >> 1 : y);
 }
 
-template <int R, bool INV>
-__device__ __forceinline__ void q_stage_r(const float2 *src, float2 *dst, int C, int L, int NS,
-                                          bool zhi, const float2 *__restrict__ tw) {
-  const int Lr = L / R, nb = C * Lr;
-  for (int idx = threadIdx.x; idx < nb; idx += kQThreads) {
-    const int c = idx / Lr, j = idx - c * Lr;
-    if (zhi) q_bfly<R, INV, true>(src, dst, c, j, L, NS, tw);
-    else q_bfly<R, INV, false>(src, dst, c, j, L, NS, tw);
+// f(c, j) for c < 2^c_log2, j < nj, spread over the workgroup's threads.
+// line_fast: consecutive threads take consecutive lines c (the side whose
+// tile of lines is contiguous); otherwise they walk along a line, 64 at a
+// time (fewer for short lines).
+template <typename F>
+__device__ __forceinline__ void q_for(int c_log2, int nj, bool line_fast, F &&f) {
+  const int tid = threadIdx.x;
+  if (line_fast) {
+    const int lc = c_log2 < 8 ? c_log2 : 8;
+    const int c0 = tid & ((1 << lc) - 1), j0 = tid >> lc;
+    for (int j = j0; j < nj; j += kQThreads >> lc)
+      for (int c = c0; c < (1 << c_log2); c += 1 << lc) f(c, j);
+  } else {
+    int lj = 6;
+    while (lj > 0 && (1 << (lj - 1)) >= nj) --lj;  // 2^lj >= nj, at most 64
+    const int j0 = tid & ((1 << lj) - 1), c0 = tid >> lj;
+    for (int c = c0; c < (1 << c_log2); c += kQThreads >> lj)
+      for (int j = j0; j < nj; j += 1 << lj) f(c, j);
   }
+}
+
+// The fields of an item's pass that its tiles use, as 32-bit values in
+// registers (every array is below 2^31 elements).
+struct QTile {
+  int in_s[3], out_s[3];
+  int kind, L, n_in, n_out, pad, ext_tile, W, tiles_a, c_log2, nrad;
+};
+
+// The stage tables of the item's transform, staged in LDS with its twiddles
+// (indexed by stage at run time, they would otherwise live in scratch).
+struct QStages {
+  int rad[kQMaxRadices], ns_shift[kQMaxRadices], ns_three[kQMaxRadices], tw_step[kQMaxRadices];
+};
+
+// One radix-R Stockham stage over the tile: butterfly j of line c reads
+// src[c][j + m L/R] and writes dst[c][(j / NS) NS R + j % NS + m NS], with
+// twiddles w^(k m) = tw[k m step], k = j % NS, from the LDS table.
+template <int R, bool INV>
+__device__ __forceinline__ void q_stage_r(const float2 *src, float2 *dst, const QTile &P, const QStages &st,
+                                          int s, bool zhi, const float2 *tw) {
+  const int L = P.L, Lr = L / R;
+  const int sh = st.ns_shift[s], th = st.ns_three[s], step = st.tw_step[s];
+  const bool first = s == 0;
+  q_for(P.c_log2, Lr, false, [&](int c, int j) {
+    const int base = c * L;
+    const int q = first ? j : qdiv(j, sh, th);
+    const int k = first ? 0 : j - q * ((th ? 3 : 1) << sh);
+    float2 x[R];
+    if (zhi && R % 2 == 0) {
+#pragma unroll
+      for (int m = 0; m < R / 2; ++m) x[m] = src[qx(base + j + m * Lr)];
+#pragma unroll
+      for (int m = R / 2; m < R; ++m) x[m] = fzero();
+      if constexpr (R % 2 == 0) dft<R, INV, true>(x);
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[m] = src[qx(base + j + m * Lr)];
+      if (!first) {
+#pragma unroll
+        for (int m = 1; m < R; ++m) x[m] = cmul_tw<INV>(x[m], tw[k * m * step]);
+      }
+      dft<R, INV, false>(x);
+    }
+    const int ns = first ? 1 : ((th ? 3 : 1) << sh);
+    const int o = base + q * ns * R + k;
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[qx(o + m * ns)] = x[m];
+  });
 }
 
 // The whole line transform of the tile in buf[cur] (result in buf[cur] on
-// return, cur updated).  zhi: the upper half of every input line is zero.
+// return, cur updated).  zhi: the upper half of every input line is zero
+// (the first stage, which has no twiddles, skips it).
 template <bool INV>
-__device__ void q_fft(float2 (*buf)[kQSlots], int &cur, const QPass &P, int C, bool zhi) {
-  int NS = 1;
+__device__ void q_fft(float2 (*buf)[kQSlots], int &cur, const QTile &P, const QStages &st, bool zhi,
+                      const float2 *tw) {
   for (int s = 0; s < P.nrad; ++s) {
-    const int R = P.rad[s];
+    const int R = st.rad[s];
     const bool z = zhi && s == 0;
     const float2 *src = buf[cur];
     float2 *dst = buf[cur ^ 1];
     switch (R) {
-      case 2: q_stage_r<2, INV>(src, dst, C, P.L, NS, z, P.tw); break;
-      case 3: q_stage_r<3, INV>(src, dst, C, P.L, NS, false, P.tw); break;
-      case 4: q_stage_r<4, INV>(src, dst, C, P.L, NS, z, P.tw); break;
-      default: q_stage_r<8, INV>(src, dst, C, P.L, NS, z, P.tw); break;
+      case 2: q_stage_r<2, INV>(src, dst, P, st, s, z, tw); break;
+      case 3: q_stage_r<3, INV>(src, dst, P, st, s, false, tw); break;
+      case 4: q_stage_r<4, INV>(src, dst, P, st, s, z, tw); break;
+      default: q_stage_r<8, INV>(src, dst, P, st, s, z, tw); break;
     }
     cur ^= 1;
-    NS *= R;
     __syncthreads();
   }
 }
 
-// Index of element j, tile line w, batch b on one side of a pass.
-__device__ __forceinline__ long long q_off(const long long *s, int j, int a, int b) {
-  return j * s[0] + a * s[1] + (long long)b * s[2];
+// Offset of element j of tile line a, batch b on one side of a pass (every
+// array is below 2^31 elements, so the sum of these non-negative terms fits).
+__device__ __forceinline__ int q_off(const int *s, int j, int a, int b) {
+  return j * s[0] + a * s[1] + b * s[2];
 }
 
 // One tile: load, transform, store.  Arrays by pass kind: P1 rho -> a1,
-// P2 a1 -> a2, P3 a2 -> a2, P4 a2 -> a1, P5 a1 -> V.
-__device__ void q_tile(float2 (*buf)[kQSlots], const QGeom &Gm, const QPass &P, const QSolve &S,
-                       int tile) {
-  const int tid = threadIdx.x;
+// P2 a1 -> a2, P3 a2 -> a2, P4 a2 -> a1, P5 a1 -> V.  tw: the pass's twiddle
+// table in LDS.
+__device__ void q_tile(float2 (*buf)[kQSlots], const float2 *tw, const QStages &st,
+                       const float *__restrict__ kf, int S_q, int kq_half, const QTile &P,
+                       const QSolve &S, int tile) {
   const int ta = tile % P.tiles_a, b = tile / P.tiles_a, a0 = ta * P.W;
-  const int C = P.C, L = P.L;
+  const int L = P.L, cl = P.c_log2;
   const bool in_line = P.in_s[0] == 1, out_line = P.out_s[0] == 1;
   int cur = 0;
   float2 *X = buf[0];
 
   if (P.kind == KIND_R2C) {
     // real lines 2c and 2c + 1 as the real and imaginary parts of line c
-    const float *in = S.rho;
-    const int W = 2 * C, n = W * L;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      int w, j;
-      if (in_line) { w = idx / L; j = idx - w * L; }
-      else { j = idx / W; w = idx - j * W; }
+    const float *__restrict__ in = S.rho;
+    q_for(cl + 1, L, !in_line, [&](int w, int j) {
       const int a = a0 + w;
       const float v = (a < P.ext_tile && j < P.n_in) ? in[q_off(P.in_s, j, a, b)] : 0.f;
       reinterpret_cast<float *>(&X[qx((w >> 1) * L + j)])[w & 1] = v;
-    }
+    });
   } else if (P.kind == KIND_C2R) {
     // Z = X_a + i X_b from the Hermitian halves of lines 2c and 2c + 1 (the
     // imaginary parts of the k = 0 and k = L/2 terms are not part of a real
     // line's spectrum and are dropped)
-    const float2 *in = S.a1;
-    const int n = C * L, h = L / 2;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      int c, j;
-      if (in_line) { c = idx / L; j = idx - c * L; }
-      else { j = idx / C; c = idx - j * C; }
+    const float2 *__restrict__ in = S.a1;
+    const int h = L / 2;
+    q_for(cl, L, !in_line, [&](int c, int j) {
       const int a = a0 + 2 * c;
       float2 z = fzero();
       if (a < P.ext_tile) {
@@ -127,51 +170,41 @@ __device__ void q_tile(float2 (*buf)[kQSlots], const QGeom &Gm, const QPass &P, 
         z = j <= h ? make_float2(xa.x - xb.y, xa.y + xb.x) : make_float2(xa.x + xb.y, xb.x - xa.y);
       }
       X[qx(c * L + j)] = z;
-    }
+    });
   } else {
-    const float2 *in = P.kind == KIND_FWD ? S.a1 : S.a2;
-    const int n = C * L;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      int c, j;
-      if (in_line) { c = idx / L; j = idx - c * L; }
-      else { j = idx / C; c = idx - j * C; }
+    const float2 *__restrict__ in = P.kind == KIND_FWD ? S.a1 : S.a2;
+    q_for(cl, L, !in_line, [&](int c, int j) {
       const int a = a0 + c;
       X[qx(c * L + j)] = (a < P.ext_tile && j < P.n_in) ? in[q_off(P.in_s, j, a, b)] : fzero();
-    }
+    });
   }
   __syncthreads();
 
-  const bool zhi = P.pad != 0;
-  if (P.kind == KIND_INV || P.kind == KIND_C2R) q_fft<true>(buf, cur, P, C, false);
-  else q_fft<false>(buf, cur, P, C, zhi);
+  if (P.kind == KIND_INV || P.kind == KIND_C2R) q_fft<true>(buf, cur, P, st, false, tw);
+  else q_fft<false>(buf, cur, P, st, P.pad != 0, tw);
 
   if (P.kind == KIND_CONV) {
     // times K^F (even along q and r): row (k_p, min(k_q, S_q - k_q))
     float2 *Y = buf[cur];
-    const int KR = L / 2 + 1, n = C * L;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      const int c = idx / L, j = idx - c * L;
+    const int KR = L / 2 + 1;
+    q_for(cl, L, false, [&](int c, int j) {
       const int kq = a0 + c;
       if (kq < P.ext_tile) {
-        const int kqf = kq <= Gm.S_q - kq ? kq : Gm.S_q - kq;
-        const float kv = Gm.kf[(long long)(b * Gm.kq_half + kqf) * KR + (j <= L - j ? j : L - j)];
-        const float2 v = Y[qx(idx)];
-        Y[qx(idx)] = make_float2(v.x * kv, v.y * kv);
+        const int kqf = kq <= S_q - kq ? kq : S_q - kq;
+        const float kv = kf[(b * kq_half + kqf) * KR + (j <= L - j ? j : L - j)];
+        const float2 v = Y[qx(c * L + j)];
+        Y[qx(c * L + j)] = make_float2(v.x * kv, v.y * kv);
       }
-    }
+    });
     __syncthreads();
-    q_fft<true>(buf, cur, P, C, false);
+    q_fft<true>(buf, cur, P, st, false, tw);
   }
 
   const float2 *Y = buf[cur];
   if (P.kind == KIND_R2C) {
     // X_a[k] = (Z[k] + conj Z[L-k]) / 2, X_b[k] = (Z[k] - conj Z[L-k]) / (2i)
-    float2 *out = S.a1;
-    const int W = 2 * C, H = P.n_out, n = W * H;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      int w, k;
-      if (out_line) { w = idx / H; k = idx - w * H; }
-      else { k = idx / W; w = idx - k * W; }
+    float2 *__restrict__ out = S.a1;
+    q_for(cl + 1, P.n_out, !out_line, [&](int w, int k) {
       const int a = a0 + w;
       if (a < P.ext_tile) {
         const int c = w >> 1;
@@ -180,30 +213,22 @@ __device__ void q_tile(float2 (*buf)[kQSlots], const QGeom &Gm, const QPass &P, 
                                  : make_float2(0.5f * (zk.x + zl.x), 0.5f * (zk.y - zl.y));
         out[q_off(P.out_s, k, a, b)] = v;
       }
-    }
+    });
   } else if (P.kind == KIND_C2R) {
-    float *out = S.V;
-    const int W = 2 * C, n = W * P.n_out;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      int w, j;
-      if (out_line) { w = idx / P.n_out; j = idx - w * P.n_out; }
-      else { j = idx / W; w = idx - j * W; }
+    float *__restrict__ out = S.V;
+    q_for(cl + 1, P.n_out, !out_line, [&](int w, int j) {
       const int a = a0 + w;
       if (a < P.ext_tile) {
         const float2 z = Y[qx((w >> 1) * L + j)];
         out[q_off(P.out_s, j, a, b)] = (w & 1) ? z.y : z.x;
       }
-    }
+    });
   } else {
-    float2 *out = P.kind == KIND_INV ? S.a1 : S.a2;
-    const int n = C * P.n_out;
-    for (int idx = tid; idx < n; idx += kQThreads) {
-      int c, j;
-      if (out_line) { c = idx / P.n_out; j = idx - c * P.n_out; }
-      else { j = idx / C; c = idx - j * C; }
+    float2 *__restrict__ out = P.kind == KIND_INV ? S.a1 : S.a2;
+    q_for(cl, P.n_out, !out_line, [&](int c, int j) {
       const int a = a0 + c;
       if (a < P.ext_tile) out[q_off(P.out_s, j, a, b)] = Y[qx(c * L + j)];
-    }
+    });
   }
   __syncthreads();  // the tile buffers are free again
 }
@@ -234,6 +259,8 @@ __device__ __forceinline__ void q_count(const QParams &a, const int *pend, int n
 // barriers, which the other lanes of its wavefront would then run alone.
 __global__ __launch_bounds__(kQThreads) void queue_kernel(QParams a) {
   __shared__ float2 buf[2][kQSlots];
+  __shared__ float2 tw[kQTwSlots];
+  __shared__ QStages st;
   __shared__ int s_item, s_full;
   __shared__ int s_pend[kQPending];
   const int tid = threadIdx.x;
@@ -243,6 +270,7 @@ __global__ __launch_bounds__(kQThreads) void queue_kernel(QParams a) {
   unsigned *segc = state + kQStateHeader;
 
   int npend = 0, pend_level = 0, acq_level = -1;
+  const float2 *tw_src = nullptr;  // the table staged in tw
   for (;;) {
     if (wave0) {
       const unsigned got = __hip_atomic_fetch_add(&state[kQHead], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -290,12 +318,36 @@ __global__ __launch_bounds__(kQThreads) void queue_kernel(QParams a) {
       if (__builtin_amdgcn_readfirstlane(s_full)) acq_level = k - 1;
     }
 
+    // the item's descriptors as values: read once, not again after every
+    // store (which the compiler could not tell apart from them)
     const QSolve S = a.solves[sg.solve];
-    const QGeom &Gm = a.geoms[S.geom];
-    const QPass &P = Gm.pass[k];
-    const int t0 = (item - sg.first) * P.G;
-    const int t1 = min(t0 + P.G, P.ntiles);
-    for (int t = t0; t < t1; ++t) q_tile(buf, Gm, P, S, t);
+    const QPass &Pg = a.geoms[S.geom].pass[k];
+    QTile P;  // the scalar fields (the stage tables go to LDS)
+    for (int i = 0; i < 3; ++i) {
+      P.in_s[i] = int(Pg.in_s[i]);
+      P.out_s[i] = int(Pg.out_s[i]);
+    }
+    P.kind = Pg.kind; P.L = Pg.L; P.n_in = Pg.n_in; P.n_out = Pg.n_out; P.pad = Pg.pad;
+    P.ext_tile = Pg.ext_tile; P.W = Pg.W; P.tiles_a = Pg.tiles_a; P.c_log2 = Pg.c_log2;
+    P.nrad = Pg.nrad;
+    const float2 *ptw = Pg.tw;
+    const int G = Pg.G, ntiles = Pg.ntiles;
+    const float *kf = a.geoms[S.geom].kf;
+    const int S_q = a.geoms[S.geom].S_q, kq_half = a.geoms[S.geom].kq_half;
+    if (ptw != tw_src) {  // (uniform: the tile loops end with a barrier)
+      for (int i = tid; i < P.L; i += kQThreads) tw[i] = ptw[i];
+      if (tid < P.nrad) {
+        st.rad[tid] = Pg.rad[tid];
+        st.ns_shift[tid] = Pg.ns_shift[tid];
+        st.ns_three[tid] = Pg.ns_three[tid];
+        st.tw_step[tid] = Pg.tw_step[tid];
+      }
+      tw_src = ptw;
+      __syncthreads();
+    }
+    const int t0 = (item - sg.first) * G;
+    const int t1 = min(t0 + G, ntiles);
+    for (int t = t0; t < t1; ++t) q_tile(buf, tw, st, kf, S_q, kq_half, P, S, t);
 
     if (tid == 0) s_pend[npend] = si;
     ++npend;
