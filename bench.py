@@ -249,6 +249,33 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     return out
 
 
+def queue_only(torch, P, dev, steps, warmup):
+    """The 512-solve float32 batch as one persistent queue launch per solve of
+    the batch: `warmup` untimed launches, then `steps` timed ones."""
+    from densities import batch_density, batch_workload
+    items = batch_workload(512)
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).to(dev)
+            for n, bc, seed in items]
+    Vs = [torch.empty_like(r) for r in rhos]
+    B = P.Batch([it[0] for it in items], [it[1] for it in items], [H] * len(items))
+    B.mode = P.POISSON_BATCH_QUEUE
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(max(warmup, 1)):  # the first launch uploads the descriptors
+        P.poisson_batch_solve(B.handle, rhos, Vs, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        P.poisson_batch_solve(B.handle, rhos, Vs, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(steps, 1)
+    alg = sum(P.poisson_plan_describe(*n, bc)["alg_bytes"] for n, bc, _ in items)
+    return {"workload": "batch512 float32, persistent queue launch", "ms": ms,
+            "solves_per_s": len(items) / (ms * 1e-3), "alg_gbs": alg / (ms * 1e-3) / 1e9,
+            "flags": B.queue_status()}
+
+
 def bench_host(torch, P, plan, r, count=20):
     """Transfer-inclusive rates (Sections 1 and 4 count the copies of rho to
     the device and of V back): one solve at a time through pinned host
@@ -471,6 +498,9 @@ def main():
                     help="skip the other configurations and the Figure 1 rows")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy (counter calibration)")
+    ap.add_argument("--queue-only", action="store_true",
+                    help="only run the 512-solve float32 batch as the persistent queue launch "
+                         "(warmup + steps launches; short runs under a profiler)")
     ap.add_argument("--fig1", action="store_true",
                     help="only run the per-BC timing relative to periodic (Figure 1) and the "
                          "axis-order study")
@@ -488,6 +518,10 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_only:
         print(json.dumps({"copy_gbs": copy_bandwidth(torch, dev)}), flush=True)
+        return
+    if args.queue_only:
+        P.load_library()
+        print(json.dumps(queue_only(torch, P, dev, args.steps, args.warmup)), flush=True)
         return
     if args.fig1:
         P.load_library()
