@@ -218,3 +218,27 @@ def test_queue_tuner_and_modes(torch_dev):
     assert e.value.code == P._lib.POISSON_E_UNSUPPORTED
     assert S.mode == P.POISSON_BATCH_GROUPED
     S.close()
+
+
+def test_queue_full_batch512(torch_dev):
+    """The whole 512-solve batch the bench times, as one queue launch: every
+    solve agrees with the grouped launches to float32 rounding (whose results
+    equal the lone solves bit for bit and meet the oracle bar in the tests
+    above), and the launch reports no flags."""
+    torch = torch_dev
+    from densities import batch_workload
+    items = batch_workload(512)
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in items]
+    G = P.Batch([c[0] for c in items], [c[1] for c in items], [H] * len(items))
+    Vg = [torch.empty_like(r) for r in rhos]
+    G.solve(rhos, Vg)
+    Q = _queue_batch(items)
+    Vq = _solve(torch, Q, rhos)
+    worst = 0.0
+    for i in range(len(items)):
+        d = float(torch.linalg.vector_norm(Vq[i] - Vg[i]) / torch.linalg.vector_norm(Vg[i]))
+        worst = max(worst, d)
+    print(f"queue batch512 vs grouped: worst relL2 {worst:.2e}", flush=True)
+    assert worst <= 5e-7
+    G.close()
+    Q.close()
