@@ -242,3 +242,24 @@ def test_queue_full_batch512(torch_dev):
     assert worst <= 5e-7
     G.close()
     Q.close()
+
+
+def test_queue_runs_isf_kernels(torch_dev):
+    """The queue takes each plan's K^F as built, so an ISF batch (free,
+    surface, wire) agrees with its grouped launches to float32 rounding."""
+    torch = torch_dev
+    cases = [((32, 32, 32), 7, 2700), ((24, 48, 12), 3, 2701), ((16, 16, 64), 2, 2702)]
+    rhos = [torch.from_numpy(batch_density(n, bc, seed).astype(np.float32)).cuda() for n, bc, seed in cases]
+    n_list, bc_list = [c[0] for c in cases], [c[1] for c in cases]
+    G = P.Batch(n_list, bc_list, [H] * len(cases), kernel="isf")
+    Vg = [torch.empty_like(r) for r in rhos]
+    G.solve(rhos, Vg)
+    Q = P.Batch(n_list, bc_list, [H] * len(cases), kernel="isf")
+    Q.mode = P.POISSON_BATCH_QUEUE
+    Vq = _solve(torch, Q, rhos)
+    for i, (n, bc, _) in enumerate(cases):
+        d = float(torch.linalg.vector_norm(Vq[i] - Vg[i]) / torch.linalg.vector_norm(Vg[i]))
+        print(f"queue isf {n} bc={bc}: {d:.2e} from the grouped launches", flush=True)
+        assert d <= 5e-7, (n, bc, d)
+    G.close()
+    Q.close()
