@@ -194,7 +194,7 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
     same = same and all(torch.equal(a, b) for a, b in zip(ref, Vs))
     B.streams = default_streams
     # float32: the persistent schedule, one launch over a pass-ordered device
-    # queue (its own line transforms: equal to the loop to float32 rounding)
+    # queue (its own engine; at the default radix choices bitwise the loop)
     queue = {}
     if precision == 0:
         B.mode = P.POISSON_BATCH_QUEUE
@@ -237,6 +237,7 @@ def bench_batch(torch, P, dev, reps=5, precision=0):
            "tuned_mode": "queue" if B.mode == P.POISSON_BATCH_QUEUE else "grouped"}
     if queue:
         out["queue_max_rel_l2_vs_loop"] = queue_diff
+        out["queue_identical_to_loop"] = queue_diff == 0.0
         out["queue_flags"] = queue_flags
     for name, t in (("loop", t_loop), ("batched", t_batch), ("batched_graph", t_graph),
                     ("batched_one_stream", t_one_stream),

@@ -359,8 +359,9 @@ int poisson_batch_get_streams(poisson_batch_t batch, int *streams);
  * The line transforms are generic in length: a tile of complex lines in LDS
  * and one Stockham step per radix (2, 3, 4, 8) in the order the radix
  * choice gives; float32 arithmetic, with the rounding of every operation
- * fixed, so a solve's result depends only on its radix choices and tile
- * shape, not on the batch it runs in.  Float32 batches only.  Every solve
+ * fixed, so a solve's result depends only on its radix choices, not on the
+ * batch it runs in or the tile shape.  At the default radix choices it is
+ * bitwise the result of the grouped launches.  Float32 batches only.  Every solve
  * gets its own intermediates (the sum of the distinct plans' workspaces
  * over all solves, allocated at the first queue solve after a change).  The
  * first queue solve after creation, a schedule change or with new arrays
@@ -374,8 +375,11 @@ int poisson_batch_get_streams(poisson_batch_t batch, int *streams);
 int poisson_batch_set_mode(poisson_batch_t batch, int mode);
 int poisson_batch_get_mode(poisson_batch_t batch, int *mode);
 /* Radix decomposition of a length-L queue transform for choice `radix_sel`:
- * 0 radix-8 stages first (then 4 or 2, then 3), 1 radix-4 stages (then 2,
- * then 3), 2 the stages of choice 0 in reverse order.  Writes the radices,
+ * 0 the stages of the grouped float32 kernels' compiled shape (radix 8
+ * first; at the default choice a queue solve computes every butterfly as
+ * the grouped launches do and gives their results bit for bit), 1 radix-4
+ * stages (then 2, then 3), 2 the stages of choice 0 in reverse order.
+ * Writes the radices,
  * first stage first, and returns their count; POISSON_E_UNSUPPORTED for a
  * length outside the library's set, POISSON_E_ARG for another choice.  Host
  * only. */

@@ -127,9 +127,11 @@ __host__ __device__ inline bool q_must_wait(int k, int acq_level) { return k > 0
 __host__ __device__ inline int q_dep_seg(int si, int nsolve) { return si - nsolve; }
 
 // Radices of a length-L line transform (L = 2^a 3^b, b <= 1, 4 <= L <= 1024)
-// for radix choice `sel`: 0 radix-8 stages first (then 4 or 2, then 3),
-// 1 radix-4 stages (then 2, then 3), 2 choice 0 in reverse order.  Returns
-// the count, 0 for an unsupported L or sel.
+// for radix choice `sel`: 0 the stages of the grouped float32 kernels'
+// compiled shape (Shape<L> of the line FFT), so a queue solve at choice 0
+// computes every butterfly as they do and gives their results bit for bit;
+// 1 radix-4 stages (then 2, then 3); 2 the stages of choice 0 in reverse
+// order.  Returns the count, 0 for an unsupported L or sel.
 __host__ __device__ inline int q_radices(int L, int sel, int *rad) {
   if (L < 4 || L > 1024 || sel < 0 || sel >= kQRadixChoices) return 0;
   int m = L, three = 0;
@@ -141,12 +143,19 @@ __host__ __device__ inline int q_radices(int L, int sel, int *rad) {
   if (sel == 1) {
     for (; e >= 2; e -= 2) rad[n++] = 4;
     if (e) rad[n++] = 2;
+    if (three) rad[n++] = 3;
+    return n;
+  }
+  // the compiled shapes: radix-8 stages, then the rest of the power of two
+  // as one radix (two radix-4 stages at 1024), then 3 before a final 2
+  if (L == 1024) {
+    rad[n++] = 8; rad[n++] = 8; rad[n++] = 4; rad[n++] = 4;
   } else {
     for (; e >= 3; e -= 3) rad[n++] = 8;
     if (e == 2) rad[n++] = 4;
+    if (three) rad[n++] = 3;
     if (e == 1) rad[n++] = 2;
   }
-  if (three) rad[n++] = 3;
   if (sel == 2)
     for (int i = 0, j = n - 1; i < j; ++i, --j) {
       const int t = rad[i]; rad[i] = rad[j]; rad[j] = t;
