@@ -717,10 +717,11 @@ constexpr int kConvWaves = 4;
 // line of the array and stores nothing) so matrix-core stages always run on
 // whole wavefronts.  With one line per wavefront the walk is scalar.
 // 24-element lanes: two wavefronts per SIMD (see the single line buffer below)
-// The fused fp16 matrix-core conv (one line per wavefront) is latency-bound:
-// keep it at four wavefronts per SIMD (128 registers; bf16 needs more).
+// The fused fp16 matrix-core conv (one line per wavefront, two transformed
+// back to back) is latency-bound: at least three wavefronts per SIMD (it
+// fits 125 registers; bf16 needs more).
 template <int L, int MODE> constexpr int conv_min_waves() {
-  return Shape<L>::E >= 24 ? 2 : (MODE == MODE_SPLIT_FP16 && engine_kind<L, MODE>() == 2 && kT<L> == 64) ? 4 : 1;
+  return Shape<L>::E >= 24 ? 2 : (MODE == MODE_SPLIT_FP16 && engine_kind<L, MODE>() == 2 && kT<L> == 64) ? 3 : 1;
 }
 
 template <int L, bool PC, int MODE>
@@ -843,7 +844,26 @@ __attribute__((amdgpu_waves_per_eu(conv_min_waves<L, MODE>()))) void conv_kernel
   Item A;
   fetch(A);
   advance();
-  if constexpr (E >= 24) {
+  if constexpr (FUSED && MODE == MODE_SPLIT_FP16) {
+    // two lines per step, transformed back to back: independent matrix-core
+    // and vector chains for the scheduler to interleave (fp16 conv at
+    // L = 512: 161 -> 155 us per launch; the bf16 conv, with three products
+    // per product and more registers, ran slower this way and keeps the
+    // alternating walk below)
+    Item B;
+    fetch(B);
+    advance();
+    while (true) {
+      process(A);
+      process(B);
+      if (!__any(B.live)) break;
+      fetch(A);
+      advance();
+      fetch(B);
+      advance();
+      if (!__any(A.live)) break;
+    }
+  } else if constexpr (E >= 24) {
     // 24 elements per lane: two items would need about 260 registers and
     // leave one wavefront per SIMD; one item, two wavefronts per SIMD
     while (true) {
