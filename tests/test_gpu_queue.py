@@ -266,3 +266,21 @@ def test_queue_runs_isf_kernels(torch_dev):
         assert torch.equal(Vq[i], Vg[i]), (n, bc)
     G.close()
     Q.close()
+
+
+def test_queue_full_free256(torch_dev):
+    """The headline problem (free 256^3, FFT grid 512^3) as a queue launch: it
+    equals the plain solve bit for bit, launch after launch."""
+    torch = torch_dev
+    from densities import workload_density
+    n, bc, rho = workload_density("free256", H)
+    r = torch.from_numpy(rho.astype(np.float32)).cuda()
+    plan = P.Plan(n, bc, H)
+    ref = plan.solve(r)
+    torch.cuda.synchronize()
+    B = _queue_batch([(n, bc, 0)])
+    for _ in range(2):
+        V = _solve(torch, B, [r])[0]
+        assert torch.equal(V, ref)
+    B.close()
+    plan.close()
